@@ -1,0 +1,45 @@
+"""Plaintext integer references (test infrastructure only).
+
+Convolution here is the CNN cross-correlation; the weight gradient is the
+correlation of the padded input with the output gradient (Section 2, "Neural
+Network Training"); all sums are exact int64 and results are finally taken
+mod t into [0, t).
+"""
+import numpy as np
+
+
+def conv2d(x, w, P):
+    """x[C, H, W], w[M, C, h, h], stride 1, zero padding P -> y[M, Ho, Wo] (int64)."""
+    C, H, W = x.shape
+    M, _, h, _ = w.shape
+    xp = np.zeros((C, H + 2 * P, W + 2 * P), dtype=np.int64)
+    xp[:, P:P + H, P:P + W] = x
+    Ho, Wo = H + 2 * P - h + 1, W + 2 * P - h + 1
+    y = np.zeros((M, Ho, Wo), dtype=np.int64)
+    for a in range(h):
+        for b in range(h):
+            patch = xp[:, a:a + Ho, b:b + Wo]            # [C, Ho, Wo]
+            y += np.einsum("mc,chw->mhw", w[:, :, a, b].astype(np.int64), patch)
+    return y
+
+
+def conv2d_weight_grad(x, dy, P, h):
+    """dW[m, c, a, b] = sum_{y,z} dy[m, y, z] * xpad[c, y+a, z+b]; x[C,H,W], dy[M,Ho,Wo]."""
+    C, H, W = x.shape
+    M, Ho, Wo = dy.shape
+    xp = np.zeros((C, H + 2 * P, W + 2 * P), dtype=np.int64)
+    xp[:, P:P + H, P:P + W] = x
+    dw = np.zeros((M, C, h, h), dtype=np.int64)
+    for a in range(h):
+        for b in range(h):
+            patch = xp[:, a:a + Ho, b:b + Wo]
+            dw[:, :, a, b] = np.einsum("myz,cyz->mc", dy.astype(np.int64), patch)
+    return dw
+
+
+def matvec(Wm, x):
+    return Wm.astype(np.int64) @ x.astype(np.int64)
+
+
+def mod_t(v, t):
+    return np.remainder(np.asarray(v, dtype=np.int64), t)
