@@ -1,0 +1,220 @@
+/*
+ * he.h -- C ABI of the MI355X homomorphic linear-layer library (libhe.so).
+ *
+ * The operations are those of CryptoTrain (arXiv 2409.16675):
+ *   - the ring A_{N,q} = Z_q[X]/(X^N+1) of Section 2 ("Notations"), held in
+ *     residue-number-system form: one plane of N coefficients per prime q_i;
+ *   - CPMul, the ciphertext x plaintext product (c0*p, c1*p) of Section 2
+ *     ("Motivation"), and CCAdd, the component-wise sum; together they form
+ *     the multiply-accumulate that the online phase of CryptoTrain-P runs on
+ *     the server (Section 3.2, c = [x](w - r_w) + [w](x - r_x) + [r_x r_w]);
+ *   - the correlation-aware packings pi_x and pi_w of Section 3.3 (Eq. 1 and
+ *     Eq. 2), extended to channels, weight gradients and FC layers;
+ *   - test-only encryption and decryption (Section 2, "HE": the homomorphic
+ *     property sigma(eps(x) o eps(y)) = sigma(eps(x (x) y))).
+ *
+ * Conventions
+ *   Layout     A plane is N contiguous uint64 coefficients; a plaintext is
+ *              [L][N]; a ciphertext is [2][L][N] (component, prime, coefficient).
+ *              Arrays of polynomials are packed back to back.
+ *   Values     Every uint64 coefficient crossing this boundary is canonical,
+ *              in [0, q_i).  Inputs outside that range give undefined results
+ *              unless HE_VALIDATE is set, in which case HE_ERANGE is returned.
+ *   Transform  he_ntt_fwd maps coefficients a_j to slots
+ *                A[k] = sum_j a_j psi^((2*brv(k)+1)*j)   (mod q_i),
+ *              brv = bit reversal over log2 N bits, psi the primitive 2N-th
+ *              root reported by he_ctx_moduli.  he_ntt_inv is its inverse.
+ *   Memory     Pointers marked "device" are device memory on the context's
+ *              device (for example the data pointer of a torch tensor); "host"
+ *              pointers are ordinary host memory.  The caller owns every buffer
+ *              and workspace it passes; the library owns only what its create
+ *              calls return.  Device calls are asynchronous on `stream` (a
+ *              hipStream_t passed as void*; NULL is the null stream) and do not
+ *              allocate device memory unless stated.
+ *   Errors     Every call returns HE_OK (0) or a negative he_status and never
+ *              aborts.  he_last_error() gives a thread-local description of the
+ *              most recent failure; HIP failures map to HE_EDEVICE.
+ *   Threads    Calls on different contexts are independent; calls that share a
+ *              context may run concurrently on different streams.
+ */
+#ifndef HE_H
+#define HE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t he_status;
+#define HE_OK 0
+#define HE_EINVAL (-1)        /* bad argument, shape or size */
+#define HE_EUNSUPPORTED (-2)  /* valid request this build does not handle */
+#define HE_ENOMEM (-3)        /* an allocation failed, or a workspace is too small */
+#define HE_EDEVICE (-4)       /* a HIP runtime call failed */
+#define HE_ERANGE (-5)        /* a coefficient outside [0, q_i) (only with HE_VALIDATE) */
+#define HE_EBUSY (-6)         /* admission refused: the job does not fit the memory cap */
+#define HE_ETIMEOUT (-7)      /* a wait ended before the job finished */
+
+typedef struct he_ctx he_ctx;
+typedef struct he_plan he_plan;
+typedef struct he_batch he_batch;
+typedef struct he_server he_server;
+
+/* Arithmetic used inside the kernels.  Results are identical (canonical
+ * residues); only speed and the admissible primes differ. */
+#define HE_ARITH_AUTO 0   /* F64 when every q_i < 2^50, else U64 */
+#define HE_ARITH_F64 1    /* exact products through fp64 FMA; needs q_i < 2^50 */
+#define HE_ARITH_U64 2    /* Shoup products through 32-bit integer multiplies; q_i < 2^62 */
+
+typedef struct {
+  uint32_t N;            /* ring degree, a power of two in [1024, 16384] */
+  uint32_t L;            /* number of primes, 1..8 */
+  uint32_t prime_bits;   /* when q == NULL: the L largest primes below 2^prime_bits with q_i = 1 mod 2N */
+  uint32_t arith;        /* HE_ARITH_* */
+  const uint64_t *q;     /* host, optional [L] explicit primes (each = 1 mod 2N, < 2^62) */
+  uint64_t t;            /* plaintext modulus, coprime to every q_i, 2 <= t < 2^32 */
+  int32_t device;        /* HIP device ordinal */
+  int32_t reserved;
+} he_params;
+
+/* Create a context: primes, roots psi_i (the smallest x with x^N = -1 mod q_i),
+ * twiddle tables and constants, uploaded to `device`.  Allocates device memory. */
+he_status he_ctx_create(const he_params *params, he_ctx **out);
+he_status he_ctx_destroy(he_ctx *ctx);
+/* Host outputs, each [L]: the primes and the roots psi_i.  Either may be NULL. */
+he_status he_ctx_moduli(const he_ctx *ctx, uint64_t *q_out, uint64_t *psi_out);
+/* Ring degree, prime count, plaintext modulus and arithmetic in use (any may be NULL). */
+he_status he_ctx_info(const he_ctx *ctx, uint32_t *N, uint32_t *L, uint64_t *t, uint32_t *arith);
+
+/* Kernel schedule used for one operation: arithmetic (HE_ARITH_F64 / HE_ARITH_U64)
+ * and log2 of the coefficients each thread holds (3, 4 or 5; the plane is split
+ * over N >> loge threads, which must be 64..1024).  Every schedule returns the
+ * same bytes; the autotuner picks the fastest.  HE_EUNSUPPORTED if not compiled
+ * for this N or if F64 is asked with a prime >= 2^50. */
+#define HE_OP_FWD 0   /* forward transforms (inputs and plaintexts) */
+#define HE_OP_INV 1   /* stand-alone inverse transforms */
+#define HE_OP_MAC 2   /* fused multiply-accumulate + inverse transform */
+he_status he_ctx_set_schedule(he_ctx *ctx, uint32_t op, uint32_t arith, uint32_t loge);
+he_status he_ctx_get_schedule(const he_ctx *ctx, uint32_t op, uint32_t *arith, uint32_t *loge);
+
+/* ---------------------------------------------------------------- transforms */
+
+/* In-place forward transform of n_polys polynomials, device planes [n_polys][L][N]. */
+he_status he_ntt_fwd(he_ctx *ctx, uint64_t *planes, uint32_t n_polys, void *stream);
+/* In-place inverse transform (exact inverse of he_ntt_fwd), same layout. */
+he_status he_ntt_inv(he_ctx *ctx, uint64_t *planes, uint32_t n_polys, void *stream);
+
+/* ------------------------------------------------------- CPMul + accumulate */
+
+/* Flags for he_cpmul_acc and he_corr_conv2d. */
+#define HE_IN_COEFF 0x0u       /* inputs in coefficient form (default) */
+#define HE_IN_NTT 0x1u         /* inputs already transformed by he_ntt_fwd */
+#define HE_OUT_COEFF 0x0u      /* output in coefficient form (default) */
+#define HE_OUT_NTT 0x2u        /* output left in transformed form */
+#define HE_OVERWRITE 0x0u      /* acc = sum (default) */
+#define HE_ACCUMULATE 0x4u     /* acc += sum; acc is read in the output form */
+#define HE_VALIDATE 0x8u       /* check that inputs are canonical (extra pass) */
+#define HE_PLAIN_RAW 0x0u      /* he_corr_conv2d: `plain` holds raw int32 weights (default) */
+#define HE_PLAIN_POLY 0x10u    /* he_corr_conv2d: `plain` holds packed int64 polynomials */
+#define HE_FUSED 0x0u          /* one fused multiply-accumulate + inverse-transform kernel (default) */
+#define HE_UNFUSED 0x20u       /* separate transform, multiply-accumulate and inverse kernels */
+
+/* CPMul + CCAdd (Section 2 "Motivation", Section 3.2):
+ *   acc_c = sum_{k<K} ct[k]_c (x) pt[k]   (ring product per prime), c = 0, 1.
+ * ct   device [K][2][L][N]     pt  device [K][L][N]     acc  device [2][L][N]
+ * ws   device workspace of at least he_cpmul_acc_ws() bytes (may be NULL if 0). */
+he_status he_cpmul_acc(he_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint32_t K, uint64_t *acc,
+                       uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+he_status he_cpmul_acc_ws(const he_ctx *ctx, uint32_t K, uint32_t flags, size_t *bytes);
+
+/* --------------------------------------------- correlation-aware convolution */
+
+#define HE_KIND_CONV 0   /* forward conv: out[b][m] = sum_k ct_in[b][k] (x) W[m][k] */
+#define HE_KIND_DW 1     /* weight gradient (CryptoTrain-P terms):
+                            out[m][k] = sum_b [X_b,k] (x) (dY_b,m - r) + [dY_b,m] (x) (X_b,k - r) */
+#define HE_KIND_FC 2     /* fully connected: out[b][o] = sum_j ct_in[b][j] (x) W[o][j] */
+
+typedef struct {
+  int32_t kind;          /* HE_KIND_* */
+  uint32_t B;            /* batch */
+  uint32_t C, M;         /* input / output channels (CONV, DW) */
+  uint32_t H, W;         /* input map (CONV, DW) */
+  uint32_t h;            /* kernel side (CONV, DW: the forward kernel) */
+  uint32_t P;            /* zero padding, stride 1 */
+  uint32_t n_in, n_out;  /* FC sizes */
+} he_conv_shape;
+
+typedef struct {
+  int32_t kind;
+  uint32_t N;
+  uint32_t O;            /* row pitch of pi_x / pi_w (Eq. 1-2): max(W,H) + h - 1 (DW: h' = H_out) */
+  uint32_t span;         /* highest product degree of one channel: (H+h-2)*O + W+h-2 */
+  uint32_t S;            /* channel stride span + 1 */
+  uint32_t Cw;           /* channels per polynomial, floor(N / S) */
+  uint32_t cb;           /* channel blocks, ceil(C / Cw) */
+  uint32_t Hout, Wout;   /* conv output map */
+  uint32_t n_iw, n_ow;   /* FC: input chunk width, outputs per polynomial */
+  uint32_t n_ct_in;      /* ciphertexts read  (CONV: B*cb; DW: B*(cb+M); FC: B*in_ct) */
+  uint32_t n_pt;         /* plaintext polynomials (CONV: M*cb; DW: B*(M+cb); FC: out_ct*in_ct) */
+  uint32_t n_ct_out;     /* ciphertexts written (CONV: B*M; DW: M*cb; FC: B*out_ct) */
+  uint32_t n_terms;      /* CPMul count */
+} he_plan_info;
+
+/* Plan a layer on a context.  Allocates host memory and a small device copy of
+ * the term lists on the context's device.  Returns
+ * HE_EUNSUPPORTED when one channel does not fit one polynomial. */
+he_status he_plan_create(const he_ctx *ctx, const he_conv_shape *shape, he_plan **out);
+he_status he_plan_destroy(he_plan *plan);
+he_status he_plan_get_info(const he_plan *plan, he_plan_info *info);
+/* Host copies of the term lists: output o sums terms [row[o], row[o+1]) of
+ * ct_in[ct_idx[t]] (x) pt[pt_idx[t]].  row [n_ct_out+1], ct_idx/pt_idx [n_terms]. */
+he_status he_plan_terms(const he_plan *plan, int32_t *row, int32_t *ct_idx, int32_t *pt_idx);
+/* Device workspace he_corr_conv2d needs with these flags. */
+he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes);
+
+/* Server side of one layer (Section 3.2 online phase with the packing of Section 3.3):
+ * transform the input ciphertexts, pack and transform the plaintexts, multiply-
+ * accumulate per the plan's term lists, inverse-transform the outputs.
+ * ct_in   device [n_ct_in][2][L][N]
+ * plain   device; HE_PLAIN_RAW: int32 weights (CONV [M][C][h][h], FC [n_out][n_in]);
+ *                 HE_PLAIN_POLY: int64 packed polynomials [n_pt][N] (signed integers,
+ *                 lifted to v mod q_i)
+ * ct_out  device [n_ct_out][2][L][N]
+ * ws      device, at least he_workspace_size() bytes. */
+he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in, const void *plain,
+                         uint64_t *ct_out, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Client-side packing (host): CONV x [B][C][H][W] -> [B][cb][N]; DW is packed as
+ * CONV with the plan's geometry; FC x [B][n_in] -> [B][in_ct][N]. */
+he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys);
+/* Client-side extraction (host): CONV [B][M][N] -> y [B][M][Hout][Wout];
+ * FC [B][out_ct][N] -> y [B][n_out]; DW [M][cb][N] -> dW [M][C][Hk][Hk] with
+ * Hk = H + 2P - Hout + 1.  Values are taken as given (mod t after decryption). */
+he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *y);
+
+/* ----------------------------------------------- test-only encryption (client) */
+
+/* BFV-style secret-key encryption (a reading of Section 2 "HE", which encrypts
+ * with a public key; secret-key encryption decrypts identically):
+ *   c1 = a,  c0 = -a*s + e + Delta*m  (mod q_i),  Delta = floor(Q / t).
+ * s device int8 [N] in {-1,0,1};  m device int64 [N] in [0,t);
+ * a device [L][N] canonical;  e device int32 [N];  ct device [2][L][N].
+ * Allocates and frees temporary device memory (not a hot-path call). */
+he_status he_encrypt(he_ctx *ctx, const int8_t *s, const int64_t *m, const uint64_t *a, const int32_t *e,
+                     uint64_t *ct, void *stream);
+/* Decryption m = round(t * [c0 + c1*s]_Q / Q) mod t of n_ct ciphertexts.
+ * s device int8 [N];  ct device [n_ct][2][L][N];  m host int64 [n_ct][N].
+ * The ring products run on the device, the exact CRT rounding on the host.
+ * Synchronises `stream`.  Allocates temporary device memory. */
+he_status he_decrypt(he_ctx *ctx, const int8_t *s, const uint64_t *ct, uint32_t n_ct, int64_t *m, void *stream);
+
+/* ------------------------------------------------------------------ errors */
+const char *he_status_str(he_status status);
+const char *he_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HE_H */

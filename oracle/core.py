@@ -41,6 +41,7 @@ def lib():
             "orc_ntt_fast": (None, [u64p, U32, U64, U64, u64p]),
             "orc_intt_fast": (None, [u64p, U32, U64, U64, u64p]),
             "orc_csr_cpmul": (None, [u64p, u64p, i32p, i32p, i32p, U32, U32, U32, u64p, u64p, u64p, ctypes.c_int]),
+            "orc_csr_cpmul_cached": (None, [u64p, u64p, U32, U32, i32p, i32p, i32p, U32, U32, U32, u64p, u64p, u64p]),
             "orc_csr_cpmul_coeff": (U64, [u64p, u64p, i32p, i32p, i32p, U32, U32, u64p, U32, U32, U32, U32]),
             "orc_ntt_planes": (None, [u64p, U32, U32, U32, u64p, u64p, u64p, ctypes.c_int]),
             "orc_negacyclic_mul_planes": (None, [u64p, u64p, U32, U32, U32, u64p, u64p]),
@@ -178,7 +179,8 @@ def csr_cpmul(ct, pt, row, ct_idx, pt_idx, q, psi, method=1):
     """Term-list multiply-accumulate (see ``orc_csr_cpmul``).
 
     ct: [n_ct, 2, L, N], pt: [n_pt, L, N]; returns [n_out, 2, L, N].
-    method 0 = schoolbook ring products, 1 = through the oracle's transform.
+    method 0 = schoolbook ring products, 1 = through the oracle's transform,
+    2 = the same with every input transformed once and cached.
     """
     ct, pct = _u64(ct)
     pt, ppt = _u64(pt)
@@ -190,7 +192,11 @@ def csr_cpmul(ct, pt, row, ct_idx, pt_idx, q, psi, method=1):
     out = np.zeros((n_out, 2, L, N), dtype=np.uint64)
     qa, pq = _u64(q)
     sa, ps = _u64(psi)
-    lib().orc_csr_cpmul(pct, ppt, prow, pci, ppi, n_out, N, L, pq, ps, out.ctypes.data_as(u64p), method)
+    if method == 2:
+        lib().orc_csr_cpmul_cached(pct, ppt, ct.shape[0], pt.shape[0], prow, pci, ppi, n_out, N, L, pq, ps,
+                                   out.ctypes.data_as(u64p))
+    else:
+        lib().orc_csr_cpmul(pct, ppt, prow, pci, ppi, n_out, N, L, pq, ps, out.ctypes.data_as(u64p), method)
     return out
 
 

@@ -276,6 +276,46 @@ void orc_csr_cpmul(const uint64_t *ct, const uint64_t *pt, const int32_t *row, c
   }
 }
 
+/* Same result as orc_csr_cpmul, with every input plane transformed once
+ * (orc_ntt_fast) and cached: out = INTT( sum_t NTT(ct) * NTT(pt) ).  Needs
+ * n_ct*2*L + n_pt*L planes of scratch, allocated here. */
+void orc_csr_cpmul_cached(const uint64_t *ct, const uint64_t *pt, uint32_t n_ct, uint32_t n_pt, const int32_t *row,
+                          const int32_t *ct_idx, const int32_t *pt_idx, uint32_t n_out, uint32_t N, uint32_t L,
+                          const uint64_t *q, const uint64_t *psi, uint64_t *out) {
+  size_t nct = (size_t)n_ct * 2 * L, npt = (size_t)n_pt * L;
+  uint64_t *fct = (uint64_t *)malloc(sizeof(uint64_t) * N * nct);
+  uint64_t *fpt = (uint64_t *)malloc(sizeof(uint64_t) * N * npt);
+#pragma omp parallel for schedule(dynamic)
+  for (long w = 0; w < (long)(nct + npt); ++w) {
+    if ((size_t)w < nct) orc_ntt_fast(ct + (size_t)w * N, N, q[w % L], psi[w % L], fct + (size_t)w * N);
+    else {
+      size_t v = (size_t)w - nct;
+      orc_ntt_fast(pt + v * N, N, q[v % L], psi[v % L], fpt + v * N);
+    }
+  }
+  long total = (long)n_out * 2 * L;
+#pragma omp parallel
+  {
+    uint64_t *facc = (uint64_t *)malloc(sizeof(uint64_t) * N);
+#pragma omp for schedule(dynamic)
+    for (long w = 0; w < total; ++w) {
+      uint32_t o = (uint32_t)(w / (2 * L));
+      uint32_t c = (uint32_t)((w / L) % 2);
+      uint32_t i = (uint32_t)(w % L);
+      for (uint32_t k = 0; k < N; ++k) facc[k] = 0;
+      for (int32_t t = row[o]; t < row[o + 1]; ++t) {
+        const uint64_t *a = fct + (((size_t)ct_idx[t] * 2 + c) * L + i) * N;
+        const uint64_t *b = fpt + ((size_t)pt_idx[t] * L + i) * N;
+        for (uint32_t k = 0; k < N; ++k) facc[k] = orc_addmod(facc[k], orc_mulmod(a[k], b[k], q[i]), q[i]);
+      }
+      orc_intt_fast(facc, N, q[i], psi[i], out + (((size_t)o * 2 + c) * L + i) * N);
+    }
+    free(facc);
+  }
+  free(fct);
+  free(fpt);
+}
+
 /* One output coefficient of orc_csr_cpmul, by the schoolbook definition (O(N * terms)). */
 uint64_t orc_csr_cpmul_coeff(const uint64_t *ct, const uint64_t *pt, const int32_t *row, const int32_t *ct_idx,
                              const int32_t *pt_idx, uint32_t N, uint32_t L, const uint64_t *q, uint32_t o,

@@ -1,0 +1,87 @@
+// Internal declarations shared by the host sources of libhe.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/he.h"
+#include "arith.hpp"
+
+namespace he {
+
+// A transform / fused-kernel schedule: arithmetic policy and threads per plane.
+struct Sched {
+  int arith;   // HE_ARITH_F64 or HE_ARITH_U64
+  int loge;    // log2 of coefficients per thread (3, 4 or 5)
+};
+
+struct Ctx {
+  uint32_t N = 0, L = 0, logN = 0;
+  uint64_t t = 0;
+  int device = 0;
+  int arith = HE_ARITH_U64;      // default policy
+  bool f64_ok = false;           // every q_i < 2^50
+  std::vector<uint64_t> q, psi;
+  std::vector<uint64_t> delta_mod;   // floor(Q / t) mod q_i
+  // device tables
+  PrimeK *d_primes = nullptr;        // [L]
+  void *d_tw_f64_fwd = nullptr;      // TwF64 [L][N]
+  void *d_tw_f64_inv = nullptr;
+  void *d_tw_u64_fwd = nullptr;      // TwU64 [L][N]
+  void *d_tw_u64_inv = nullptr;
+  // schedules chosen per operation (autotuner may change them)
+  Sched s_fwd{HE_ARITH_U64, 4}, s_inv{HE_ARITH_U64, 4}, s_mac{HE_ARITH_U64, 4};
+};
+
+// thread-local error text
+void set_error(const std::string &msg);
+he_status fail(he_status st, const std::string &msg);
+he_status hip_fail(hipError_t e, const char *what);
+
+// ------------------------------------------------------------------ launchers
+// All return hipSuccess or the launch error.  Planes [n][L][N]; prime of plane p is p % L.
+hipError_t launch_ntt_fwd(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
+                          hipStream_t st);
+hipError_t launch_ntt_fwd_lift(const Ctx &c, const Sched &s, uint64_t *out, const int64_t *polys, uint32_t n_polys,
+                               hipStream_t st);
+hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
+                          hipStream_t st);
+// Term-list multiply-accumulate in the transformed domain followed by the
+// inverse transform (fused), or left transformed (out_ntt).  Output plane
+// (o, comp, i) = sum_t ct_hat[cti[t]][comp][i] * pt_hat[pti[t]][i].
+// With row == nullptr there is one output and terms t = 0..K-1 (identity lists).
+struct Terms {
+  const int32_t *row = nullptr, *cti = nullptr, *pti = nullptr;
+  uint32_t n_out = 1;
+  uint32_t K = 0;   // identity mode only
+};
+hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct_hat, const uint64_t *pt_hat,
+                      const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st);
+
+hipError_t launch_zero_i64(int64_t *p, size_t n, hipStream_t st);
+hipError_t launch_pack_conv_w(int64_t *polys, const int32_t *w, uint32_t M, uint32_t C, uint32_t h, uint32_t O,
+                              uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, hipStream_t st);
+hipError_t launch_pack_fc_w(int64_t *polys, const int32_t *W, uint32_t n_out, uint32_t n_in, uint32_t n_iw,
+                            uint32_t n_ow, uint32_t in_ct, uint32_t N, hipStream_t st);
+// validation: count of coefficients >= q_i in [n][L][N] planes, written to *bad (device)
+hipError_t launch_check_canonical(const Ctx &c, const uint64_t *planes, size_t n_planes, uint32_t *bad,
+                                  hipStream_t st);
+
+// encryption helpers
+template <class T>
+hipError_t launch_lift(const Ctx &c, uint64_t *out, const T *v, hipStream_t st);   // [N] -> [L][N]
+hipError_t launch_pmul_bcast(const Ctx &c, uint64_t *out, const uint64_t *x, const uint64_t *y, uint32_t n_planes,
+                             hipStream_t st);   // out[p] = x[p] * y[p % L]
+hipError_t launch_add_planes(const Ctx &c, uint64_t *out, const uint64_t *a, const uint64_t *b, uint32_t n_planes,
+                             hipStream_t st);
+hipError_t launch_enc_combine(const Ctx &c, uint64_t *c0, const uint64_t *prod, const int32_t *e, const int64_t *m,
+                              const uint64_t *delta_w /*device [2L]: w, w'*/, hipStream_t st);
+hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, size_t n, hipStream_t st);
+
+// Schedules compiled into the library for a ring degree (used by the autotuner and tests).
+std::vector<Sched> schedules_for(uint32_t logN, bool f64_ok);
+bool sched_valid(uint32_t logN, const Sched &s);
+
+}  // namespace he

@@ -1,0 +1,580 @@
+// gfx950 kernels of libhe.so: transforms, fused multiply-accumulate + inverse
+// transform, plaintext packing, and the small helpers used by encryption.
+#include "he_internal.hpp"
+#include "ntt.hpp"
+
+namespace he {
+
+// ------------------------------------------------------------------ policies
+template <class A> struct TwOf;
+template <> struct TwOf<ArF64> { using T = TwF64; };
+template <> struct TwOf<ArU64> { using T = TwU64; };
+
+template <class A>
+__device__ __forceinline__ uint64_t canon_add(const A &, uint64_t a, uint64_t b, uint64_t q) {
+  uint64_t s = a + b;
+  return s >= q ? s - q : s;
+}
+
+// -------------------------------------------------------------- transforms
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT) void k_ntt_fwd(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
+                                                       const PrimeK *__restrict__ primes,
+                                                       const typename A::Tw *__restrict__ tw, int L) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int plane = blockIdx.x;
+  const int i = plane % L;
+  const A ar(primes[i]);
+  const uint64_t *src = in + (size_t)plane * G::N;
+  uint64_t *dst = out + (size_t)plane * G::N;
+  const int tid = threadIdx.x;
+  auto ld = [&](int k) { return ar.load(src[k]); };
+  auto st = [&](int k, uint64_t v) { dst[k] = v; };
+  ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+}
+
+// Forward transform of signed integer polynomials lifted to every prime:
+// plane p reads polynomial p / L and lifts it modulo q_{p % L}.
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT) void k_ntt_fwd_lift(uint64_t *__restrict__ out,
+                                                            const int64_t *__restrict__ polys,
+                                                            const PrimeK *__restrict__ primes,
+                                                            const typename A::Tw *__restrict__ tw, int L) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int plane = blockIdx.x;
+  const int i = plane % L;
+  const A ar(primes[i]);
+  const int64_t *src = polys + (size_t)(plane / L) * G::N;
+  uint64_t *dst = out + (size_t)plane * G::N;
+  const int tid = threadIdx.x;
+  auto ld = [&](int k) { return ar.load_signed(src[k]); };
+  auto st = [&](int k, uint64_t v) { dst[k] = v; };
+  ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+}
+
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT) void k_ntt_inv(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
+                                                       const PrimeK *__restrict__ primes,
+                                                       const typename A::Tw *__restrict__ tw, int L) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int plane = blockIdx.x;
+  const int i = plane % L;
+  const A ar(primes[i]);
+  const uint64_t *src = in + (size_t)plane * G::N;
+  uint64_t *dst = out + (size_t)plane * G::N;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) {
+    const int k = j * G::NT + tid;
+    lds[lpad(k)] = ar.load(src[k]);
+  }
+  auto st = [&](int k, uint64_t v) { dst[k] = v; };
+  ntt_inverse_from_lds<A, G, 100>(ar, tw + (size_t)i * G::N, tid, lds, st);
+}
+
+// ------------------------------------------------- multiply-accumulate (slots)
+// Sum over a term list of slot-wise products, returned as a policy value with
+// bound A::kReduced (F64) or canonical (U64).
+template <class A>
+struct MacAcc;
+
+// fp64: each product has |p| <= 0.76 q; after a fold |acc| <= 0.51 q, so a chunk
+// of 8 products keeps |acc| <= 6.6 q < 7 q.
+template <>
+struct MacAcc<ArF64> {
+  static constexpr int kChunk = 8;
+  double acc = 0.0;
+  __device__ __forceinline__ void init(const PrimeK *) {}
+  __device__ __forceinline__ void add(const ArF64 &ar, uint64_t a, uint64_t b) { acc += ar.mulv((double)a, (double)b); }
+  __device__ __forceinline__ void fold(const ArF64 &ar) { acc = ar.reduce(acc); }
+  __device__ __forceinline__ double value() const { return acc; }
+};
+
+// integer: 128-bit sums of products < 2^124; a folded value (< q) plus 15
+// products stays below 2^128.  fold: hi * (2^64 mod q) + lo, canonical.
+template <>
+struct MacAcc<ArU64> {
+  static constexpr int kChunk = 15;
+  uint64_t lo = 0, hi = 0;
+  const PrimeK *pk = nullptr;
+  __device__ __forceinline__ void init(const PrimeK *p) { pk = p; }
+  __device__ __forceinline__ void add(const ArU64 &, uint64_t a, uint64_t b) {
+    const uint64_t pl = a * b, ph = __umul64hi(a, b);
+    const uint64_t nl = lo + pl;
+    hi += ph + (nl < lo ? 1u : 0u);
+    lo = nl;
+  }
+  __device__ __forceinline__ void fold(const ArU64 &ar) {
+    uint64_t x = ar.mul(hi, pk->r64, pk->r64s) + ar.mul(lo, 1, pk->one_s);   // < 4q
+    x = x >= ar.two_q ? x - ar.two_q : x;
+    x = x >= ar.q ? x - ar.q : x;
+    lo = x;
+    hi = 0;
+  }
+  __device__ __forceinline__ uint64_t value() const { return lo; }
+};
+
+struct TermArgs {
+  const int32_t *row, *cti, *pti;
+  uint32_t K;     // identity mode (row == nullptr): one output, terms 0..K-1
+};
+
+__device__ __forceinline__ void term_range(const TermArgs &ta, int o, int &t0, int &t1) {
+  if (ta.row) {
+    t0 = ta.row[o];
+    t1 = ta.row[o + 1];
+  } else {
+    t0 = 0;
+    t1 = (int)ta.K;
+  }
+}
+__device__ __forceinline__ int term_ct(const TermArgs &ta, int t) { return ta.row ? ta.cti[t] : t; }
+__device__ __forceinline__ int term_pt(const TermArgs &ta, int t) { return ta.row ? ta.pti[t] : t; }
+
+// One workgroup per output plane (o, comp, i): multiply-accumulate the slots in
+// linear order into LDS, then the inverse transform, then store (or add).
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT) void k_mac_inv(uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat,
+                                                       const uint64_t *__restrict__ pt_hat, TermArgs ta,
+                                                       const PrimeK *__restrict__ primes,
+                                                       const typename A::Tw *__restrict__ tw, int L, int accumulate) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int plane = blockIdx.x;   // (o * 2 + comp) * L + i
+  const int i = plane % L;
+  const int comp = (plane / L) & 1;
+  const int o = plane / (2 * L);
+  const PrimeK *pk = primes + i;
+  const A ar(*pk);
+  const int tid = threadIdx.x;
+  int t0, t1;
+  term_range(ta, o, t0, t1);
+  MacAcc<A> acc[G::E];
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) acc[j].init(pk);
+  for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
+    const int te = min(t + MacAcc<A>::kChunk, t1);
+    for (int tt = t; tt < te; ++tt) {
+      const uint64_t *a = ct_hat + ((size_t)(term_ct(ta, tt) * 2 + comp) * L + i) * G::N;
+      const uint64_t *b = pt_hat + ((size_t)term_pt(ta, tt) * L + i) * G::N;
+#pragma unroll
+      for (int j = 0; j < G::E; ++j) {
+        const int k = j * G::NT + tid;
+        acc[j].add(ar, a[k], b[k]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) acc[j].fold(ar);
+  }
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) lds[lpad(j * G::NT + tid)] = acc[j].value();
+  uint64_t *dst = out + (size_t)plane * G::N;
+  const uint64_t q = pk->q;
+  if (accumulate) {
+    auto st = [&](int k, uint64_t v) { dst[k] = canon_add(ar, dst[k], v, q); };
+    ntt_inverse_from_lds<A, G, 51>(ar, tw + (size_t)i * G::N, tid, lds, st);
+  } else {
+    auto st = [&](int k, uint64_t v) { dst[k] = v; };
+    ntt_inverse_from_lds<A, G, 51>(ar, tw + (size_t)i * G::N, tid, lds, st);
+  }
+}
+
+// Multiply-accumulate left in the transformed domain: one thread per slot.
+template <class A>
+__global__ __launch_bounds__(256) void k_mac_slots(uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat,
+                                                   const uint64_t *__restrict__ pt_hat, TermArgs ta,
+                                                   const PrimeK *__restrict__ primes, int L, int N, int accumulate) {
+  const int plane = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int i = plane % L;
+  const int comp = (plane / L) & 1;
+  const int o = plane / (2 * L);
+  const PrimeK *pk = primes + i;
+  const A ar(*pk);
+  int t0, t1;
+  term_range(ta, o, t0, t1);
+  MacAcc<A> acc;
+  acc.init(pk);
+  for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
+    const int te = min(t + MacAcc<A>::kChunk, t1);
+    for (int tt = t; tt < te; ++tt) {
+      const uint64_t a = ct_hat[((size_t)(term_ct(ta, tt) * 2 + comp) * L + i) * N + k];
+      const uint64_t b = pt_hat[((size_t)term_pt(ta, tt) * L + i) * N + k];
+      acc.add(ar, a, b);
+    }
+    acc.fold(ar);
+  }
+  uint64_t v = ar.store(acc.value());
+  uint64_t *dst = out + (size_t)plane * N + k;
+  *dst = accumulate ? canon_add(ar, *dst, v, pk->q) : v;
+}
+
+// ---------------------------------------------------------------- packing
+__global__ void k_zero_i64(int64_t *p, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = 0;
+}
+
+// Weights w[M][C][h][h] -> polynomials [M][cb][N]: channel c of block c / Cw at
+// offset -(c mod Cw) * S (stored at N - cc*S + p with the sign flipped, X^N = -1),
+// within a channel w[a][b] at (h-1-a)*O + (h-1-b)  (pi_w, Eq. 2).
+__global__ void k_pack_conv_w(int64_t *__restrict__ polys, const int32_t *__restrict__ w, uint32_t M, uint32_t C,
+                              uint32_t h, uint32_t O, uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N) {
+  const size_t total = (size_t)M * C * h * h;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t b = id % h, a = (id / h) % h, c = (id / ((size_t)h * h)) % C, m = id / ((size_t)h * h * C);
+    const uint32_t blk = c / Cw, cc = c % Cw;
+    const uint32_t p = (h - 1 - a) * O + (h - 1 - b);
+    int64_t *poly = polys + ((size_t)m * cb + blk) * N;
+    const int64_t v = w[id];
+    if (cc == 0) poly[p] = v;
+    else poly[N - cc * S + p] = -v;
+  }
+}
+
+// FC weights W[n_out][n_in] -> [out_ct][in_ct][N]: W[i][j] at ii*n_iw + n_iw-1-jj.
+__global__ void k_pack_fc_w(int64_t *__restrict__ polys, const int32_t *__restrict__ W, uint32_t n_out, uint32_t n_in,
+                            uint32_t n_iw, uint32_t n_ow, uint32_t in_ct, uint32_t N) {
+  const size_t total = (size_t)n_out * n_in;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t j = id % n_in, i = id / n_in;
+    const uint32_t ko = i / n_ow, ii = i % n_ow, ki = j / n_iw, jj = j % n_iw;
+    polys[((size_t)ko * in_ct + ki) * N + ii * n_iw + n_iw - 1 - jj] = W[id];
+  }
+}
+
+__global__ void k_check_canonical(const uint64_t *__restrict__ planes, size_t n_planes, const PrimeK *primes, int L,
+                                  int N, uint32_t *bad) {
+  const size_t total = n_planes * (size_t)N;
+  uint32_t cnt = 0;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x)
+    cnt += planes[id] >= primes[(id / N) % L].q ? 1u : 0u;
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+// ---------------------------------------------------------- encryption helpers
+template <class T>
+__global__ void k_lift(uint64_t *__restrict__ out, const T *__restrict__ v, const PrimeK *primes, int L, int N) {
+  const int total = L * N;
+  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+    const int i = id / N, k = id % N;
+    const int64_t x = (int64_t)v[k];
+    const int64_t q = (int64_t)primes[i].q;
+    int64_t r = x % q;
+    out[id] = (uint64_t)(r < 0 ? r + q : r);
+  }
+}
+
+__device__ __forceinline__ uint64_t mulmod_u128(uint64_t a, uint64_t b, const PrimeK &pk) {
+  // a, b < q < 2^62: 128-bit product folded as in MacAcc<ArU64>
+  const ArU64 ar(pk);
+  const uint64_t lo = a * b, hi = __umul64hi(a, b);
+  uint64_t x = ar.mul(hi, pk.r64, pk.r64s) + ar.mul(lo, 1, pk.one_s);
+  x = x >= ar.two_q ? x - ar.two_q : x;
+  return x >= pk.q ? x - pk.q : x;
+}
+
+__global__ void k_pmul_bcast(uint64_t *__restrict__ out, const uint64_t *__restrict__ x, const uint64_t *__restrict__ y,
+                             const PrimeK *primes, int L, int N, size_t n_planes) {
+  const size_t total = n_planes * N;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
+    const int i = (id / N) % L, k = id % N;
+    out[id] = mulmod_u128(x[id], y[(size_t)i * N + k], primes[i]);
+  }
+}
+
+__global__ void k_add_planes(uint64_t *__restrict__ out, const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
+                             const PrimeK *primes, int L, int N, size_t n_planes) {
+  const size_t total = n_planes * N;
+  for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t q = primes[(id / N) % L].q;
+    const uint64_t s = a[id] + b[id];
+    out[id] = s >= q ? s - q : s;
+  }
+}
+
+// c0 = -prod + e + (Delta mod q_i) * m  (mod q_i); delta_w = [w_0..w_{L-1}, w'_0..w'_{L-1}] (Shoup)
+__global__ void k_enc_combine(uint64_t *__restrict__ c0, const uint64_t *__restrict__ prod, const int32_t *__restrict__ e,
+                              const int64_t *__restrict__ m, const uint64_t *__restrict__ delta_w, const PrimeK *primes,
+                              int L, int N) {
+  const int total = L * N;
+  for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < total; id += gridDim.x * blockDim.x) {
+    const int i = id / N, k = id % N;
+    const PrimeK &pk = primes[i];
+    const ArU64 ar(pk);
+    const uint64_t q = pk.q;
+    uint64_t dm = ar.mul((uint64_t)m[k], delta_w[i], delta_w[L + i]);   // [0, 2q)
+    dm = dm >= q ? dm - q : dm;
+    const int64_t ev = e[k];
+    const uint64_t er = ev < 0 ? q - (uint64_t)(-ev) : (uint64_t)ev;
+    uint64_t s = dm + er;
+    s = s >= q ? s - q : s;
+    const uint64_t p = prod[id];
+    s = s >= p ? s - p : s + q - p;
+    c0[id] = s;
+  }
+}
+
+__global__ void k_copy_u64(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src, size_t n) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+// --------------------------------------------------------------- dispatch
+static inline unsigned grid_for(size_t n, unsigned block) {
+  size_t g = (n + block - 1) / block;
+  if (g > 65535u * 4u) g = 65535u * 4u;
+  return (unsigned)(g ? g : 1);
+}
+
+// Set the dynamic-LDS limit once per kernel instantiation.
+template <class Kern>
+static hipError_t prep(Kern k, size_t lds) {
+  static thread_local const void *done[512];
+  static thread_local int nd = 0;
+  for (int j = 0; j < nd; ++j)
+    if (done[j] == (const void *)k) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess && nd < 512) done[nd++] = (const void *)k;
+  return e;
+}
+
+template <class A>
+static const typename A::Tw *tw_ptr(const Ctx &c, bool inverse);
+template <>
+const TwF64 *tw_ptr<ArF64>(const Ctx &c, bool inverse) {
+  return (const TwF64 *)(inverse ? c.d_tw_f64_inv : c.d_tw_f64_fwd);
+}
+template <>
+const TwU64 *tw_ptr<ArU64>(const Ctx &c, bool inverse) {
+  return (const TwU64 *)(inverse ? c.d_tw_u64_inv : c.d_tw_u64_fwd);
+}
+
+enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV };
+
+struct LaunchArgs {
+  uint64_t *out;
+  const uint64_t *in;
+  const int64_t *polys;
+  const uint64_t *pt;
+  TermArgs ta;
+  int accumulate;
+  unsigned grid;
+};
+
+template <class A, int LOGN, int LOGT>
+static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t st) {
+  using G = Geo<LOGN, LOGT>;
+  const size_t lds = (size_t)G::LDS_WORDS * 8;
+  hipError_t e;
+  switch (op) {
+    case OP_FWD:
+      if ((e = prep(k_ntt_fwd<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_fwd<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, c.d_primes,
+                         tw_ptr<A>(c, false), (int)c.L);
+      break;
+    case OP_FWD_LIFT:
+      if ((e = prep(k_ntt_fwd_lift<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_fwd_lift<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.polys,
+                         c.d_primes, tw_ptr<A>(c, false), (int)c.L);
+      break;
+    case OP_INV:
+      if ((e = prep(k_ntt_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_inv<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, c.d_primes,
+                         tw_ptr<A>(c, true), (int)c.L);
+      break;
+    case OP_MAC_INV:
+      if ((e = prep(k_mac_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.pt, la.ta,
+                         c.d_primes, tw_ptr<A>(c, true), (int)c.L, la.accumulate);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <class A, int LOGN>
+static hipError_t run_loge(const Ctx &c, int loge, Op op, const LaunchArgs &la, hipStream_t st) {
+  if constexpr (LOGN - 3 <= 10) {
+    if (loge == 3) return run_op<A, LOGN, LOGN - 3>(c, op, la, st);
+  }
+  if constexpr (LOGN - 4 >= 6 && LOGN - 4 <= 10) {
+    if (loge == 4) return run_op<A, LOGN, LOGN - 4>(c, op, la, st);
+  }
+  if constexpr (LOGN - 5 >= 6 && LOGN - 5 <= 10) {
+    if (loge == 5) return run_op<A, LOGN, LOGN - 5>(c, op, la, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class A>
+static hipError_t run_logn(const Ctx &c, int loge, Op op, const LaunchArgs &la, hipStream_t st) {
+  switch (c.logN) {
+    case 10: return run_loge<A, 10>(c, loge, op, la, st);
+    case 11: return run_loge<A, 11>(c, loge, op, la, st);
+    case 12: return run_loge<A, 12>(c, loge, op, la, st);
+    case 13: return run_loge<A, 13>(c, loge, op, la, st);
+    case 14: return run_loge<A, 14>(c, loge, op, la, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static hipError_t dispatch(const Ctx &c, const Sched &s, Op op, const LaunchArgs &la, hipStream_t st) {
+  if (la.grid == 0) return hipSuccess;
+  if (s.arith == HE_ARITH_F64) {
+    if (!c.f64_ok) return hipErrorInvalidValue;
+    return run_logn<ArF64>(c, s.loge, op, la, st);
+  }
+  return run_logn<ArU64>(c, s.loge, op, la, st);
+}
+
+bool sched_valid(uint32_t logN, const Sched &s) {
+  const int logt = (int)logN - s.loge;
+  if (logN < 10 || logN > 14) return false;
+  if (s.loge < 3 || s.loge > 5) return false;
+  return logt >= 6 && logt <= 10;
+}
+
+std::vector<Sched> schedules_for(uint32_t logN, bool f64_ok) {
+  std::vector<Sched> v;
+  for (int a : {HE_ARITH_F64, HE_ARITH_U64}) {
+    if (a == HE_ARITH_F64 && !f64_ok) continue;
+    for (int le = 3; le <= 5; ++le) {
+      Sched s{a, le};
+      if (sched_valid(logN, s)) v.push_back(s);
+    }
+  }
+  return v;
+}
+
+hipError_t launch_ntt_fwd(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
+                          hipStream_t st) {
+  LaunchArgs la{};
+  la.out = out;
+  la.in = in;
+  la.grid = n_planes;
+  return dispatch(c, s, OP_FWD, la, st);
+}
+
+hipError_t launch_ntt_fwd_lift(const Ctx &c, const Sched &s, uint64_t *out, const int64_t *polys, uint32_t n_polys,
+                               hipStream_t st) {
+  LaunchArgs la{};
+  la.out = out;
+  la.polys = polys;
+  la.grid = n_polys * c.L;
+  return dispatch(c, s, OP_FWD_LIFT, la, st);
+}
+
+hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
+                          hipStream_t st) {
+  LaunchArgs la{};
+  la.out = out;
+  la.in = in;
+  la.grid = n_planes;
+  return dispatch(c, s, OP_INV, la, st);
+}
+
+hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct_hat, const uint64_t *pt_hat,
+                      const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st) {
+  TermArgs ta{tm.row, tm.cti, tm.pti, tm.K};
+  const uint32_t n_planes = tm.n_out * 2 * c.L;
+  if (n_planes == 0) return hipSuccess;
+  if (out_ntt) {
+    dim3 grid((c.N + 255) / 256, n_planes);
+    if (s.arith == HE_ARITH_F64 && c.f64_ok)
+      hipLaunchKernelGGL(k_mac_slots<ArF64>, grid, dim3(256), 0, st, out, ct_hat, pt_hat, ta, c.d_primes, (int)c.L,
+                         (int)c.N, accumulate ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_mac_slots<ArU64>, grid, dim3(256), 0, st, out, ct_hat, pt_hat, ta, c.d_primes, (int)c.L,
+                         (int)c.N, accumulate ? 1 : 0);
+    return hipGetLastError();
+  }
+  LaunchArgs la{};
+  la.out = out;
+  la.in = ct_hat;
+  la.pt = pt_hat;
+  la.ta = ta;
+  la.accumulate = accumulate ? 1 : 0;
+  la.grid = n_planes;
+  return dispatch(c, s, OP_MAC_INV, la, st);
+}
+
+hipError_t launch_zero_i64(int64_t *p, size_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_conv_w(int64_t *polys, const int32_t *w, uint32_t M, uint32_t C, uint32_t h, uint32_t O,
+                              uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, hipStream_t st) {
+  const size_t total = (size_t)M * C * h * h;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_conv_w, dim3(grid_for(total, 256)), dim3(256), 0, st, polys, w, M, C, h, O, S, Cw, cb, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_fc_w(int64_t *polys, const int32_t *W, uint32_t n_out, uint32_t n_in, uint32_t n_iw,
+                            uint32_t n_ow, uint32_t in_ct, uint32_t N, hipStream_t st) {
+  const size_t total = (size_t)n_out * n_in;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_fc_w, dim3(grid_for(total, 256)), dim3(256), 0, st, polys, W, n_out, n_in, n_iw, n_ow,
+                     in_ct, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_canonical(const Ctx &c, const uint64_t *planes, size_t n_planes, uint32_t *bad,
+                                  hipStream_t st) {
+  const size_t total = n_planes * c.N;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_check_canonical, dim3(grid_for(total, 256)), dim3(256), 0, st, planes, n_planes, c.d_primes,
+                     (int)c.L, (int)c.N, bad);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_lift(const Ctx &c, uint64_t *out, const T *v, hipStream_t st) {
+  const size_t total = (size_t)c.L * c.N;
+  hipLaunchKernelGGL(k_lift<T>, dim3(grid_for(total, 256)), dim3(256), 0, st, out, v, c.d_primes, (int)c.L, (int)c.N);
+  return hipGetLastError();
+}
+template hipError_t launch_lift<int8_t>(const Ctx &, uint64_t *, const int8_t *, hipStream_t);
+template hipError_t launch_lift<int32_t>(const Ctx &, uint64_t *, const int32_t *, hipStream_t);
+template hipError_t launch_lift<int64_t>(const Ctx &, uint64_t *, const int64_t *, hipStream_t);
+
+hipError_t launch_pmul_bcast(const Ctx &c, uint64_t *out, const uint64_t *x, const uint64_t *y, uint32_t n_planes,
+                             hipStream_t st) {
+  const size_t total = (size_t)n_planes * c.N;
+  hipLaunchKernelGGL(k_pmul_bcast, dim3(grid_for(total, 256)), dim3(256), 0, st, out, x, y, c.d_primes, (int)c.L,
+                     (int)c.N, (size_t)n_planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_planes(const Ctx &c, uint64_t *out, const uint64_t *a, const uint64_t *b, uint32_t n_planes,
+                             hipStream_t st) {
+  const size_t total = (size_t)n_planes * c.N;
+  hipLaunchKernelGGL(k_add_planes, dim3(grid_for(total, 256)), dim3(256), 0, st, out, a, b, c.d_primes, (int)c.L,
+                     (int)c.N, (size_t)n_planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_enc_combine(const Ctx &c, uint64_t *c0, const uint64_t *prod, const int32_t *e, const int64_t *m,
+                              const uint64_t *delta_w, hipStream_t st) {
+  const size_t total = (size_t)c.L * c.N;
+  hipLaunchKernelGGL(k_enc_combine, dim3(grid_for(total, 256)), dim3(256), 0, st, c0, prod, e, m, delta_w, c.d_primes,
+                     (int)c.L, (int)c.N);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, size_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace he

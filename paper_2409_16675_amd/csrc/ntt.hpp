@@ -1,0 +1,287 @@
+// Negacyclic number-theoretic transform of one plane per workgroup, gfx950.
+//
+// Forward: Cooley-Tukey butterflies with the powers of psi merged into the
+// twiddles (table entry k = psi^brv(k)), natural-order input, bit-reversed
+// output, so slot k holds a(psi^(2 brv(k) + 1)).  Inverse: Gentleman-Sande
+// butterflies with psi^-1 powers in the same order, N^-1 folded into the last
+// stage (table entries 0 and 1), bit-reversed input, natural output.
+//
+// Work split: a plane of N = 2^LOGN coefficients is held by NT = 2^LOGT
+// threads, E = N / NT coefficients each in registers.  The LOGN stages are
+// cut into passes of at most LOGE = log2 E stages.  In a pass with first
+// stage S0 and R stages the index bits are [S0 high bits | R pass bits | rest]
+// and each thread owns whole radix-2^R groups (the pass bits live in the
+// register index), so a pass needs no communication; between passes the
+// plane goes through LDS (padded by one word every 32 to spread banks).  The
+// first forward pass reads HBM directly and the last inverse pass writes HBM
+// directly: in both the thread index maps to the low index bits, so those
+// accesses are coalesced.  The bit-reversed side goes through LDS.
+#pragma once
+#include "arith.hpp"
+
+namespace he {
+
+template <int LOGN_, int LOGT_>
+struct Geo {
+  static constexpr int LOGN = LOGN_, LOGT = LOGT_;
+  static constexpr int N = 1 << LOGN, NT = 1 << LOGT, LOGE = LOGN - LOGT, E = 1 << LOGE;
+  static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
+  static constexpr int s0(int k) { return k * LOGE; }
+  static constexpr int r(int k) { return (LOGN - k * LOGE) < LOGE ? (LOGN - k * LOGE) : LOGE; }
+  static constexpr int LDS_WORDS = N + (N >> 5);
+};
+
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+
+// Index of register slot (g, p) of thread tid in a pass starting at stage S0 with R stages.
+template <int LOGN, int LOGT, int S0, int R>
+__device__ __forceinline__ int pass_index(int tid, int g, int p) {
+  constexpr int NLOW = LOGN - S0 - R;
+  const int f = (g << LOGT) | tid;
+  const int low = f & ((1 << NLOW) - 1);
+  const int high = f >> NLOW;
+  return (high << (LOGN - S0)) | (p << NLOW) | low;
+}
+
+// ---------------------------------------------------------------- bound bookkeeping
+// For the lazily reduced fp64 policy: worst-case |value| / q through a pass,
+// and the stages before which every register is reduced.  Integer policy
+// bounds are fixed by construction (kLimit is huge), so no reduction is placed.
+struct PassPlan {
+  unsigned mask;   // bit u: reduce all registers before stage u
+  double b_out;
+};
+
+template <class A>
+constexpr PassPlan plan_ct(int R, double b_in) {
+  PassPlan p{0u, b_in};
+  double b = b_in;
+  for (int u = 0; u < R; ++u) {
+    double nb = b + A::mul_out(b);
+    if (nb > A::kLimit) {
+      p.mask |= 1u << u;
+      b = A::kReduced;
+      nb = b + A::mul_out(b);
+    }
+    b = nb;
+  }
+  p.b_out = b;
+  return p;
+}
+
+template <class A>
+constexpr PassPlan plan_gs(int R, double b_in) {
+  PassPlan p{0u, b_in};
+  double b = b_in;
+  for (int u = 0; u < R; ++u) {
+    double s = 2.0 * b;
+    double nb = s > A::mul_out(s) ? s : A::mul_out(s);
+    if (s > A::kLimit || nb > A::kLimit) {
+      p.mask |= 1u << u;
+      b = A::kReduced;
+      s = 2.0 * b;
+      nb = s > A::mul_out(s) ? s : A::mul_out(s);
+    }
+    b = nb;
+  }
+  p.b_out = b;
+  return p;
+}
+
+// Bound entering forward pass k (passes run 0, 1, ..., each starting from the previous output).
+template <class A, class G>
+constexpr double fwd_bound_in(int k) {
+  double b = A::kCanon;
+  for (int j = 0; j < k; ++j) b = plan_ct<A>(G::r(j), b).b_out;
+  return b;
+}
+// Inverse passes run k = NPASS-1 down to 0; the input is canonical (or a reduced accumulator).
+template <class A, class G>
+constexpr double inv_bound_in(int k, double b0) {
+  double b = b0;
+  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs<A>(G::r(j), b).b_out;
+  return b;
+}
+
+// ------------------------------------------------------------------- butterflies
+template <class A>
+__device__ __forceinline__ void gs_bfly(const A &ar, typename A::V &x, typename A::V &y, typename A::Tw w);
+
+template <>
+__device__ __forceinline__ void gs_bfly<ArF64>(const ArF64 &ar, double &x, double &y, TwF64 w) {
+  double d = x - y;
+  x = x + y;
+  y = ar.mul(d, w);
+}
+template <>
+__device__ __forceinline__ void gs_bfly<ArU64>(const ArU64 &ar, uint64_t &x, uint64_t &y, TwU64 w) {
+  // x, y in [0, 2q) -> x + y in [0, 2q), (x - y) w in [0, 2q)
+  uint64_t s = x + y;
+  s = s >= ar.two_q ? s - ar.two_q : s;
+  uint64_t d = x - y + ar.two_q;
+  y = ar.mul(d, w);
+  x = s;
+}
+// Last inverse stage with N^-1 folded in: x' = (x + y) n, y' = (x - y) (w n).
+template <class A>
+__device__ __forceinline__ void gs_last(const A &ar, typename A::V &x, typename A::V &y, typename A::Tw n,
+                                        typename A::Tw wn);
+template <>
+__device__ __forceinline__ void gs_last<ArF64>(const ArF64 &ar, double &x, double &y, TwF64 n, TwF64 wn) {
+  double d = x - y;
+  double s = x + y;
+  x = ar.mul(s, n);
+  y = ar.mul(d, wn);
+}
+template <>
+__device__ __forceinline__ void gs_last<ArU64>(const ArU64 &ar, uint64_t &x, uint64_t &y, TwU64 n, TwU64 wn) {
+  uint64_t s = x + y;               // < 4q < 2^64
+  uint64_t d = x - y + ar.two_q;    // < 4q
+  x = ar.mul(s, n);
+  y = ar.mul(d, wn);
+}
+
+template <class A>
+__device__ __forceinline__ typename A::V reduce_gs_in(const A &ar, typename A::V v) {
+  return ar.reduce(v);
+}
+
+// ------------------------------------------------------------------------ passes
+// Forward pass K.  `ld(i)` yields the value at plane index i, `st(i, v)` stores it.
+template <class A, class G, int K, class Ld, class St>
+__device__ __forceinline__ void fwd_pass(const A &ar, const typename A::Tw *__restrict__ tw, int tid, Ld ld, St st) {
+  using V = typename A::V;
+  constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
+  constexpr PassPlan pp = plan_ct<A>(R, fwd_bound_in<A, G>(K));
+  static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
+  V v[G::E];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p));
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if ((pp.mask >> u) & 1u) {
+#pragma unroll
+      for (int e = 0; e < G::E; ++e) v[e] = ar.reduce(v[e]);
+    }
+    const int s = S0 + u;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int high = ((g << G::LOGT) | tid) >> NLOW;
+#pragma unroll
+      for (int p = 0; p < (1 << R); ++p) {
+        if (p & (1 << (R - 1 - u))) continue;
+        const int p2 = p | (1 << (R - 1 - u));
+        const typename A::Tw w = tw[(1 << s) + ((high << u) | (p >> (R - u)))];
+        ar.ct(v[(g << R) | p], v[(g << R) | p2], w);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int p = 0; p < (1 << R); ++p) st(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p), v[(g << R) | p]);
+}
+
+// Inverse pass K (stages S0+R-1 down to S0).  B0 is the bound of the transform's input.
+template <class A, class G, int K, int B0X100, class Ld, class St>
+__device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__restrict__ tw, int tid, Ld ld, St st) {
+  using V = typename A::V;
+  constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
+  constexpr PassPlan pp = plan_gs<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
+  V v[G::E];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p));
+#pragma unroll
+  for (int uu = 0; uu < R; ++uu) {
+    const int u = R - 1 - uu;   // stage S0 + u, processed from the highest down
+    if ((pp.mask >> uu) & 1u) {
+#pragma unroll
+      for (int e = 0; e < G::E; ++e) v[e] = ar.reduce(v[e]);
+    }
+    const int s = S0 + u;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int high = ((g << G::LOGT) | tid) >> NLOW;
+#pragma unroll
+      for (int p = 0; p < (1 << R); ++p) {
+        if (p & (1 << (R - 1 - u))) continue;
+        const int p2 = p | (1 << (R - 1 - u));
+        if (s == 0) {
+          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], tw[0], tw[1]);
+        } else {
+          const typename A::Tw w = tw[(1 << s) + ((high << u) | (p >> (R - u)))];
+          gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], w);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int p = 0; p < (1 << R); ++p) st(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p), v[(g << R) | p]);
+}
+
+// A pass loads and stores the same thread-private set of indices, so passes
+// sharing LDS need only one barrier between them.
+
+// Forward passes K..NPASS-1, LDS to LDS.
+template <class A, class G, int K>
+__device__ __forceinline__ void fwd_lds_passes(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
+                                               typename A::V *lds) {
+  if constexpr (K < G::NPASS) {
+    __syncthreads();
+    auto ld = [&](int i) { return lds[lpad(i)]; };
+    auto st = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
+    fwd_pass<A, G, K>(ar, tw, tid, ld, st);
+    fwd_lds_passes<A, G, K + 1>(ar, tw, tid, lds);
+  }
+}
+
+// Inverse passes K down to 1, LDS to LDS (pass 0 is run by the caller, to HBM).
+template <class A, class G, int K, int B0X100>
+__device__ __forceinline__ void inv_lds_passes(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
+                                               typename A::V *lds) {
+  if constexpr (K >= 1) {
+    __syncthreads();
+    auto ld = [&](int i) { return lds[lpad(i)]; };
+    auto st = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
+    inv_pass<A, G, K, B0X100>(ar, tw, tid, ld, st);
+    inv_lds_passes<A, G, K - 1, B0X100>(ar, tw, tid, lds);
+  }
+}
+
+// Whole forward transform: ld(i) reads coefficient i of the input (coalesced
+// pass-0 order), the result is written through st(i, canonical) in linear order.
+template <class A, class G, class Ld, class St>
+__device__ __forceinline__ void ntt_forward(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
+                                            typename A::V *lds, Ld ld, St st) {
+  static_assert(G::NPASS >= 2, "at least two passes");
+  auto st_lds = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
+  fwd_pass<A, G, 0>(ar, tw, tid, ld, st_lds);
+  fwd_lds_passes<A, G, 1>(ar, tw, tid, lds);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) {
+    const int i = j * G::NT + tid;
+    st(i, ar.store(lds[lpad(i)]));
+  }
+}
+
+// Whole inverse transform of values already placed in LDS (linear order, bound
+// B0X100/100 q); pass 0 writes st(i, canonical) in coalesced order.
+template <class A, class G, int B0X100, class St>
+__device__ __forceinline__ void ntt_inverse_from_lds(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
+                                                     typename A::V *lds, St st) {
+  static_assert(G::NPASS >= 2, "at least two passes");
+  inv_lds_passes<A, G, G::NPASS - 1, B0X100>(ar, tw, tid, lds);
+  __syncthreads();
+  auto ld = [&](int i) { return lds[lpad(i)]; };
+  auto st_out = [&](int i, typename A::V v) { st(i, ar.store(v)); };
+  inv_pass<A, G, 0, B0X100>(ar, tw, tid, ld, st_out);
+}
+
+}  // namespace he

@@ -1,0 +1,107 @@
+// Layer planner: packing geometry and CPMul term lists for conv, weight-gradient
+// and FC layers (correlation-aware packing of Section 3.3, Eq. 1 and Eq. 2).
+#include "plan.hpp"
+
+#include <algorithm>
+
+namespace he {
+
+static uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+he_status make_plan(const Ctx &c, const he_conv_shape &s, Plan &p) {
+  p.shape = s;
+  he_plan_info &in = p.info;
+  in = he_plan_info{};
+  in.kind = s.kind;
+  in.N = c.N;
+  const uint32_t N = c.N;
+  p.row.clear();
+  p.cti.clear();
+  p.pti.clear();
+  if (s.B == 0) return fail(HE_EINVAL, "batch must be positive");
+  if (s.kind == HE_KIND_CONV || s.kind == HE_KIND_DW) {
+    if (!s.C || !s.M || !s.H || !s.W || !s.h) return fail(HE_EINVAL, "conv sizes must be positive");
+    if (s.H + 2 * s.P < s.h || s.W + 2 * s.P < s.h) return fail(HE_EINVAL, "kernel larger than padded input");
+    if (s.P >= s.h) return fail(HE_EINVAL, "padding must be smaller than the kernel");
+    in.Hout = s.H + 2 * s.P - s.h + 1;
+    in.Wout = s.W + 2 * s.P - s.h + 1;
+    // the polynomial "kernel" is w (h x h) for CONV and dY (Hout x Hout) for DW
+    uint32_t hk = s.h;
+    if (s.kind == HE_KIND_DW) {
+      if (in.Hout != in.Wout) return fail(HE_EUNSUPPORTED, "weight gradient needs a square output map");
+      hk = in.Hout;
+    }
+    p.hk = hk;
+    in.O = std::max(s.W, s.H) + hk - 1;
+    in.span = (s.H + hk - 2) * in.O + (s.W + hk - 2);
+    in.S = in.span + 1;
+    if (in.S > N) return fail(HE_EUNSUPPORTED, "one channel does not fit one polynomial (needs spatial windows)");
+    in.Cw = N / in.S;
+    in.cb = cdiv(s.C, in.Cw);
+    if (s.kind == HE_KIND_CONV) {
+      in.n_ct_in = s.B * in.cb;
+      in.n_pt = s.M * in.cb;
+      in.n_ct_out = s.B * s.M;
+      p.row.push_back(0);
+      for (uint32_t b = 0; b < s.B; ++b)
+        for (uint32_t m = 0; m < s.M; ++m) {
+          for (uint32_t k = 0; k < in.cb; ++k) {
+            p.cti.push_back((int32_t)(b * in.cb + k));
+            p.pti.push_back((int32_t)(m * in.cb + k));
+          }
+          p.row.push_back((int32_t)p.cti.size());
+        }
+    } else {
+      // ct [B][cb + M] = ([X_b,k] blocks, [dY_b,m]); pt [B][M + cb] = ((dY-r)_b,m, (X-r)_b,k); out [M][cb]
+      const uint32_t cb = in.cb, M = s.M;
+      in.n_ct_in = s.B * (cb + M);
+      in.n_pt = s.B * (M + cb);
+      in.n_ct_out = M * cb;
+      p.row.push_back(0);
+      for (uint32_t m = 0; m < M; ++m)
+        for (uint32_t k = 0; k < cb; ++k) {
+          for (uint32_t b = 0; b < s.B; ++b) {
+            p.cti.push_back((int32_t)(b * (cb + M) + k));
+            p.pti.push_back((int32_t)(b * (M + cb) + m));
+            p.cti.push_back((int32_t)(b * (cb + M) + cb + m));
+            p.pti.push_back((int32_t)(b * (M + cb) + M + k));
+          }
+          p.row.push_back((int32_t)p.cti.size());
+        }
+    }
+  } else if (s.kind == HE_KIND_FC) {
+    if (!s.n_in || !s.n_out) return fail(HE_EINVAL, "FC sizes must be positive");
+    uint64_t best_key[3] = {~0ull, ~0ull, ~0ull};
+    for (uint32_t iw = 1; iw <= std::min(s.n_in, N); ++iw) {
+      const uint32_t cap = (N + 1) / iw;
+      if (cap < 2) break;
+      const uint32_t ow = std::min(s.n_out, cap - 1);
+      const uint32_t ict = cdiv(s.n_in, iw), oct = cdiv(s.n_out, ow);
+      const uint64_t key[3] = {(uint64_t)ict * oct, ict, oct};
+      if (std::lexicographical_compare(key, key + 3, best_key, best_key + 3)) {
+        std::copy(key, key + 3, best_key);
+        in.n_iw = iw;
+        in.n_ow = ow;
+      }
+    }
+    const uint32_t ict = cdiv(s.n_in, in.n_iw), oct = cdiv(s.n_out, in.n_ow);
+    in.n_ct_in = s.B * ict;
+    in.n_pt = oct * ict;
+    in.n_ct_out = s.B * oct;
+    p.row.push_back(0);
+    for (uint32_t b = 0; b < s.B; ++b)
+      for (uint32_t o = 0; o < oct; ++o) {
+        for (uint32_t j = 0; j < ict; ++j) {
+          p.cti.push_back((int32_t)(b * ict + j));
+          p.pti.push_back((int32_t)(o * ict + j));
+        }
+        p.row.push_back((int32_t)p.cti.size());
+      }
+  } else {
+    return fail(HE_EINVAL, "unknown layer kind");
+  }
+  in.n_terms = (uint32_t)p.cti.size();
+  return HE_OK;
+}
+
+}  // namespace he

@@ -1,0 +1,319 @@
+"""Thin ctypes binding of libhe.so (C ABI in include/he.h), same names as the C calls.
+
+Only argument marshalling happens here: device buffers are torch tensors (their
+data pointers are passed through), streams are torch streams.  Every step of
+the computation runs in the library's HIP kernels.  If libhe.so is missing the
+import fails loudly: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhe.so is not built (run paper_2409_16675_amd.build.build() or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+HE_OK = 0
+HE_EINVAL, HE_EUNSUPPORTED, HE_ENOMEM, HE_EDEVICE, HE_ERANGE, HE_EBUSY, HE_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
+HE_ARITH_AUTO, HE_ARITH_F64, HE_ARITH_U64 = 0, 1, 2
+HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC = 0, 1, 2
+
+c_void_p, c_u32, c_u64, c_i32, c_size = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i32p = ctypes.POINTER(ctypes.c_int32)
+i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class he_params(ctypes.Structure):
+    _fields_ = [("N", c_u32), ("L", c_u32), ("prime_bits", c_u32), ("arith", c_u32), ("q", u64p), ("t", c_u64),
+                ("device", c_i32), ("reserved", c_i32)]
+
+
+class he_conv_shape(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("B", c_u32), ("C", c_u32), ("M", c_u32), ("H", c_u32), ("W", c_u32), ("h", c_u32),
+                ("P", c_u32), ("n_in", c_u32), ("n_out", c_u32)]
+
+
+class he_plan_info(ctypes.Structure):
+    _fields_ = [(n, c_i32 if n == "kind" else c_u32) for n in
+                ("kind", "N", "O", "span", "S", "Cw", "cb", "Hout", "Wout", "n_iw", "n_ow", "n_ct_in", "n_pt",
+                 "n_ct_out", "n_terms")]
+
+
+_SIGS = {
+    "he_ctx_create": [ctypes.POINTER(he_params), ctypes.POINTER(c_void_p)],
+    "he_ctx_destroy": [c_void_p],
+    "he_ctx_moduli": [c_void_p, u64p, u64p],
+    "he_ctx_info": [c_void_p, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32), ctypes.POINTER(c_u64),
+                    ctypes.POINTER(c_u32)],
+    "he_ctx_set_schedule": [c_void_p, c_u32, c_u32, c_u32],
+    "he_ctx_get_schedule": [c_void_p, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
+    "he_ntt_fwd": [c_void_p, c_void_p, c_u32, c_void_p],
+    "he_ntt_inv": [c_void_p, c_void_p, c_u32, c_void_p],
+    "he_cpmul_acc": [c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_u32, c_void_p, c_size, c_void_p],
+    "he_cpmul_acc_ws": [c_void_p, c_u32, c_u32, ctypes.POINTER(c_size)],
+    "he_plan_create": [c_void_p, ctypes.POINTER(he_conv_shape), ctypes.POINTER(c_void_p)],
+    "he_plan_destroy": [c_void_p],
+    "he_plan_get_info": [c_void_p, ctypes.POINTER(he_plan_info)],
+    "he_plan_terms": [c_void_p, i32p, i32p, i32p],
+    "he_workspace_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
+    "he_corr_conv2d": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
+    "he_pack_input": [c_void_p, i32p, i64p],
+    "he_extract_output": [c_void_p, i64p, i64p],
+    "he_encrypt": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "he_decrypt": [c_void_p, c_void_p, c_void_p, c_u32, i64p, c_void_p],
+}
+for _n, _a in _SIGS.items():
+    _f = getattr(_lib, _n)
+    _f.argtypes = _a
+    _f.restype = c_i32
+_lib.he_status_str.argtypes = [c_i32]
+_lib.he_status_str.restype = ctypes.c_char_p
+_lib.he_last_error.argtypes = []
+_lib.he_last_error.restype = ctypes.c_char_p
+
+EXPORTED = sorted(list(_SIGS) + ["he_status_str", "he_last_error"])
+
+
+class HeError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s: %s (%s)" % (where, _lib.he_status_str(status).decode(), _lib.he_last_error().decode()))
+
+
+def _chk(st, where):
+    if st != HE_OK:
+        raise HeError(st, where)
+
+
+def _stream(stream):
+    if stream is None:
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return c_void_p(stream)
+    return c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if t.numel() and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return c_void_p(t.data_ptr())
+    return c_void_p(t)
+
+
+def lib():
+    return _lib
+
+
+# ------------------------------------------------------------------ contexts
+def he_ctx_create(N, L, prime_bits=50, t=65537, q=None, arith=HE_ARITH_AUTO, device=0):
+    p = he_params()
+    p.N, p.L, p.prime_bits, p.arith, p.t, p.device = N, L, prime_bits, arith, t, device
+    qa = None
+    if q is not None:
+        qa = (c_u64 * L)(*[int(v) for v in q])
+        p.q = ctypes.cast(qa, u64p)
+    h = c_void_p()
+    _chk(_lib.he_ctx_create(ctypes.byref(p), ctypes.byref(h)), "he_ctx_create")
+    return h
+
+
+def he_ctx_destroy(ctx):
+    _chk(_lib.he_ctx_destroy(ctx), "he_ctx_destroy")
+
+
+def he_ctx_moduli(ctx, L):
+    q = (c_u64 * L)()
+    psi = (c_u64 * L)()
+    _chk(_lib.he_ctx_moduli(ctx, ctypes.cast(q, u64p), ctypes.cast(psi, u64p)), "he_ctx_moduli")
+    return [int(v) for v in q], [int(v) for v in psi]
+
+
+def he_ctx_info(ctx):
+    N, L, a = c_u32(), c_u32(), c_u32()
+    t = c_u64()
+    _chk(_lib.he_ctx_info(ctx, ctypes.byref(N), ctypes.byref(L), ctypes.byref(t), ctypes.byref(a)), "he_ctx_info")
+    return N.value, L.value, t.value, a.value
+
+
+HE_OP_FWD, HE_OP_INV, HE_OP_MAC = 0, 1, 2
+
+
+def he_ctx_set_schedule(ctx, op, arith, loge):
+    _chk(_lib.he_ctx_set_schedule(ctx, op, arith, loge), "he_ctx_set_schedule")
+
+
+def he_ctx_get_schedule(ctx, op):
+    a, le = c_u32(), c_u32()
+    _chk(_lib.he_ctx_get_schedule(ctx, op, ctypes.byref(a), ctypes.byref(le)), "he_ctx_get_schedule")
+    return a.value, le.value
+
+
+def compiled_schedules(N, f64_ok=True):
+    """(arith, loge) pairs compiled for ring degree N (mirrors the library's table)."""
+    logn = N.bit_length() - 1
+    out = []
+    for a in (HE_ARITH_F64, HE_ARITH_U64):
+        if a == HE_ARITH_F64 and not f64_ok:
+            continue
+        for le in (3, 4, 5):
+            if 10 <= logn <= 14 and 6 <= logn - le <= 10:
+                out.append((a, le))
+    return out
+
+
+def he_ntt_fwd(ctx, planes, n_polys, stream=None):
+    _chk(_lib.he_ntt_fwd(ctx, _ptr(planes), n_polys, _stream(stream)), "he_ntt_fwd")
+
+
+def he_ntt_inv(ctx, planes, n_polys, stream=None):
+    _chk(_lib.he_ntt_inv(ctx, _ptr(planes), n_polys, _stream(stream)), "he_ntt_inv")
+
+
+def he_cpmul_acc_ws(ctx, K, flags=0):
+    b = c_size()
+    _chk(_lib.he_cpmul_acc_ws(ctx, K, flags, ctypes.byref(b)), "he_cpmul_acc_ws")
+    return b.value
+
+
+def he_cpmul_acc(ctx, ct, pt, K, acc, flags=0, ws=None, ws_bytes=0, stream=None):
+    _chk(_lib.he_cpmul_acc(ctx, _ptr(ct), _ptr(pt), K, _ptr(acc), flags, _ptr(ws), ws_bytes, _stream(stream)),
+         "he_cpmul_acc")
+
+
+# ------------------------------------------------------------------ plans
+def he_plan_create(ctx, kind, B=1, C=0, M=0, H=0, W=0, h=0, P=0, n_in=0, n_out=0):
+    s = he_conv_shape(kind, B, C, M, H, W, h, P, n_in, n_out)
+    h_ = c_void_p()
+    _chk(_lib.he_plan_create(ctx, ctypes.byref(s), ctypes.byref(h_)), "he_plan_create")
+    return h_
+
+
+def he_plan_destroy(plan):
+    _chk(_lib.he_plan_destroy(plan), "he_plan_destroy")
+
+
+def he_plan_get_info(plan):
+    i = he_plan_info()
+    _chk(_lib.he_plan_get_info(plan, ctypes.byref(i)), "he_plan_get_info")
+    return {n: getattr(i, n) for n, _ in he_plan_info._fields_}
+
+
+def he_plan_terms(plan):
+    info = he_plan_get_info(plan)
+    row = np.zeros(info["n_ct_out"] + 1, np.int32)
+    cti = np.zeros(info["n_terms"], np.int32)
+    pti = np.zeros(info["n_terms"], np.int32)
+    _chk(_lib.he_plan_terms(plan, row.ctypes.data_as(i32p), cti.ctypes.data_as(i32p), pti.ctypes.data_as(i32p)),
+         "he_plan_terms")
+    return row, cti, pti
+
+
+def he_workspace_size(plan, flags=0):
+    b = c_size()
+    _chk(_lib.he_workspace_size(plan, flags, ctypes.byref(b)), "he_workspace_size")
+    return b.value
+
+
+def he_corr_conv2d(ctx, plan, ct_in, plain, ct_out, flags=0, ws=None, ws_bytes=0, stream=None):
+    _chk(_lib.he_corr_conv2d(ctx, plan, _ptr(ct_in), _ptr(plain), _ptr(ct_out), flags, _ptr(ws), ws_bytes,
+                             _stream(stream)), "he_corr_conv2d")
+
+
+def he_pack_input(plan, x, n_out_words):
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    out = np.zeros(n_out_words, dtype=np.int64)
+    _chk(_lib.he_pack_input(plan, x.ctypes.data_as(i32p), out.ctypes.data_as(i64p)), "he_pack_input")
+    return out
+
+
+def he_extract_output(plan, polys, n_out_values):
+    polys = np.ascontiguousarray(polys, dtype=np.int64)
+    y = np.zeros(n_out_values, dtype=np.int64)
+    _chk(_lib.he_extract_output(plan, polys.ctypes.data_as(i64p), y.ctypes.data_as(i64p)), "he_extract_output")
+    return y
+
+
+# ------------------------------------------------------------------ encryption
+def he_encrypt(ctx, s, m, a, e, ct, stream=None):
+    _chk(_lib.he_encrypt(ctx, _ptr(s), _ptr(m), _ptr(a), _ptr(e), _ptr(ct), _stream(stream)), "he_encrypt")
+
+
+def he_decrypt(ctx, s, ct, n_ct, N, stream=None):
+    m = np.zeros(n_ct * N, dtype=np.int64)
+    _chk(_lib.he_decrypt(ctx, _ptr(s), _ptr(ct), n_ct, m.ctypes.data_as(i64p), _stream(stream)), "he_decrypt")
+    return m.reshape(n_ct, N)
+
+
+# ------------------------------------------------------------------ helpers
+def to_device_u64(a, device="cuda"):
+    """numpy uint64 array -> contiguous torch.uint64 tensor on the GPU."""
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device).view(torch.uint64)
+
+
+def to_numpy_u64(t):
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+def empty_u64(shape, device="cuda"):
+    return torch.empty(shape, dtype=torch.int64, device=device).view(torch.uint64)
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class Context:
+    """Owns an he_ctx handle."""
+
+    def __init__(self, N, L, prime_bits=50, t=65537, q=None, arith=HE_ARITH_AUTO, device=0):
+        self.h = he_ctx_create(N, L, prime_bits, t, q, arith, device)
+        self.N, self.L, self.t, self.arith = he_ctx_info(self.h)
+        self.q, self.psi = he_ctx_moduli(self.h, self.L)
+
+    def close(self):
+        if self.h:
+            he_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Owns an he_plan handle."""
+
+    def __init__(self, ctx, kind, **shape):
+        self.ctx = ctx
+        self.shape = dict(shape)
+        self.kind = kind
+        self.h = he_plan_create(ctx.h, kind, **shape)
+        self.info = he_plan_get_info(self.h)
+
+    def workspace_size(self, flags=0):
+        return he_workspace_size(self.h, flags)
+
+    def close(self):
+        if self.h:
+            he_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,107 @@
+"""GPU parity: context constants and transforms against the oracle, bit for bit.
+
+Every compiled schedule (fp64 and integer arithmetic, 8/16/32 coefficients per
+thread) is run on the same seeded planes; all must equal the oracle's transform
+(itself pinned to the evaluation definition).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import core
+from paper_2409_16675_amd import synth
+from tests.helpers import assert_equal_u64
+
+RINGS = [(1024, 2, 50), (2048, 2, 50), (2048, 2, 54), (4096, 2, 50), (8192, 3, 50), (8192, 3, 60), (16384, 4, 50)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,bits", RINGS)
+def test_ctx_constants_match_oracle(gpu_lib, N, L, bits):
+    he = gpu_lib
+    ctx = he.Context(N, L, prime_bits=bits)
+    q, psi = core.params(N, L, bits)
+    assert ctx.q == q and ctx.psi == psi
+    assert ctx.arith == (he.HE_ARITH_F64 if bits <= 50 else he.HE_ARITH_U64)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,bits", RINGS)
+def test_ntt_every_schedule_matches_oracle(gpu_lib, N, L, bits):
+    he = gpu_lib
+    ctx = he.Context(N, L, prime_bits=bits)
+    g = synth.rng(90, N + L + bits)
+    n_polys = 3
+    x = synth.uniform_residues(g, (n_polys,), ctx.q, N)
+    expect = core.ntt_planes(x, ctx.q, ctx.psi)
+    for arith, loge in he.compiled_schedules(N, f64_ok=bits <= 50):
+        print("case N=%d L=%d bits=%d arith=%d loge=%d" % (N, L, bits, arith, loge), flush=True)
+        he.he_ctx_set_schedule(ctx.h, he.HE_OP_FWD, arith, loge)
+        he.he_ctx_set_schedule(ctx.h, he.HE_OP_INV, arith, loge)
+        d = he.to_device_u64(x)
+        he.he_ntt_fwd(ctx.h, d, n_polys)
+        torch.cuda.synchronize()
+        assert_equal_u64(he.to_numpy_u64(d), expect, "fwd %d/%d" % (arith, loge))
+        he.he_ntt_inv(ctx.h, d, n_polys)
+        torch.cuda.synchronize()
+        assert_equal_u64(he.to_numpy_u64(d), x, "inv %d/%d" % (arith, loge))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 50), (4096, 2, 60), (16384, 4, 50)])
+def test_ntt_edge_values(gpu_lib, N, L, bits):
+    he = gpu_lib
+    ctx = he.Context(N, L, prime_bits=bits)
+    qs = np.array(ctx.q, dtype=np.uint64)[:, None]
+    zeros = np.zeros((L, N), np.uint64)
+    top = np.broadcast_to(qs - np.uint64(1), (L, N)).copy()
+    alt = top.copy()
+    alt[:, ::2] = 0
+    one_hot = zeros.copy()
+    one_hot[:, N - 1] = qs[:, 0] - np.uint64(1)
+    x = np.stack([zeros, top, alt, one_hot])
+    expect = core.ntt_planes(x, ctx.q, ctx.psi)
+    for arith, loge in he.compiled_schedules(N, f64_ok=bits <= 50):
+        print("case edge N=%d arith=%d loge=%d" % (N, arith, loge), flush=True)
+        he.he_ctx_set_schedule(ctx.h, he.HE_OP_FWD, arith, loge)
+        he.he_ctx_set_schedule(ctx.h, he.HE_OP_INV, arith, loge)
+        d = he.to_device_u64(x)
+        he.he_ntt_fwd(ctx.h, d, 4)
+        torch.cuda.synchronize()
+        assert_equal_u64(he.to_numpy_u64(d), expect, "fwd edge")
+        he.he_ntt_inv(ctx.h, d, 4)
+        torch.cuda.synchronize()
+        assert_equal_u64(he.to_numpy_u64(d), x, "inv edge")
+
+
+@pytest.mark.gpu
+def test_ntt_empty_batch_is_a_no_op(gpu_lib):
+    he = gpu_lib
+    ctx = he.Context(8192, 3)
+    d = he.empty_u64((1,))
+    he.he_ntt_fwd(ctx.h, d, 0)
+    he.he_ntt_inv(ctx.h, d, 0)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_ntt_large_batch_sampled_against_definition(gpu_lib):
+    # the launch shape of the benchmark: many planes at N = 8192; a sample of slots
+    # is checked against the evaluation definition, one coefficient at a time
+    he = gpu_lib
+    N, L = 8192, 3
+    ctx = he.Context(N, L)
+    g = synth.rng(91, 1)
+    n_polys = 512
+    x = synth.uniform_residues(g, (n_polys,), ctx.q, N)
+    d = he.to_device_u64(x)
+    he.he_ntt_fwd(ctx.h, d, n_polys)
+    torch.cuda.synchronize()
+    y = he.to_numpy_u64(d)
+    rs = np.random.Generator(np.random.PCG64(5))
+    for _ in range(24):
+        p, i, k = int(rs.integers(n_polys)), int(rs.integers(L)), int(rs.integers(N))
+        assert int(y[p, i, k]) == core.ntt_coeff(x[p, i], ctx.q[i], ctx.psi[i], k)
+    he.he_ntt_inv(ctx.h, d, n_polys)
+    torch.cuda.synchronize()
+    assert_equal_u64(he.to_numpy_u64(d), x, "roundtrip")

@@ -176,7 +176,9 @@ def test_csr_cpmul_methods_agree_and_coeff_matches():
     pti = np.array([1, 0, 3, 2, 1, 0, 3], np.int32)
     o0 = core.csr_cpmul(ct, pt, row, cti, pti, q, psi, method=0)
     o1 = core.csr_cpmul(ct, pt, row, cti, pti, q, psi, method=1)
+    o2 = core.csr_cpmul(ct, pt, row, cti, pti, q, psi, method=2)
     assert np.array_equal(o0, o1)
+    assert np.array_equal(o0, o2)
     assert not o0[1].any()                         # an output with no terms is zero
     # against Python big ints, term by term
     for o in range(3):
