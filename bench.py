@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark: CPMul-accumulates per second of the correlation-aware conv layer on one MI355X.
+
+Workload (one step): the server side of one conv2d forward layer -- batch 16 of
+3x32x32 integer activations packed with pi_x and encrypted, 16 output channels,
+3x3 kernel, stride 1, pad 1, int8 weights packed with pi_w; ring degree 8192,
+3 primes (50-bit); 256 CPMul-accumulates producing 256 output ciphertexts.
+Every step transforms the 16 input ciphertexts, packs and transforms the 16
+weight polynomials, multiply-accumulates and inverse-transforms the outputs.
+
+Prints one JSON line.  `value` is the whole-job CPMul-accumulate rate of the
+default (fused / batched) path with inputs already resident in HBM; the plain
+per-layer path (separate transform, multiply-accumulate and inverse kernels)
+is reported beside it, as are transforms per second, the roofline of the
+dominant kernel (timed with HIP events on its launch stream during the timed
+region) and the CPU oracle timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CPMul-accumulates/s at N=8192,L=3 (batched vs plain); p50/p99 job latency"
+PEAK_HBM_GBS = 8000.0
+# fp64 and 32-bit integer VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# minimal VALU instruction counts of the exact fp64 arithmetic
+OPS_MODMUL = 6          # mul, fma, mul, rndne, fma, add
+OPS_BFLY = OPS_MODMUL + 2
+OPS_MAC_TERM = OPS_MODMUL + 2   # quotient companion mul + accumulate add
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+def workload(he, synth, torch):
+    N, L, B, C, M, H, W, h, P = 8192, 3, 16, 3, 16, 32, 32, 3, 1
+    ctx = he.Context(N, L, prime_bits=50)
+    plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=W, h=h, P=P)
+    info = plan.info
+    x = synth.int8_uniform(synth.rng(2, synth.STREAM_ACT), (B, C, H, W))
+    w = synth.int8_uniform(synth.rng(2, synth.STREAM_PT), (M, C, h, h))
+    polys = he.he_pack_input(plan.h, x.reshape(-1), B * info["cb"] * N).reshape(-1, N)
+    # encrypt on the device with the library (client side, outside the timed region)
+    import numpy as np
+    s = synth.ternary(synth.rng(2, synth.STREAM_SK), N)
+    ga, ge = synth.rng(2, synth.STREAM_A), synth.rng(2, synth.STREAM_E)
+    ct_in = he.empty_u64((polys.shape[0], 2, L, N))
+    ds = torch.from_numpy(s.astype(np.int8)).cuda()
+    for k in range(polys.shape[0]):
+        a = he.to_device_u64(synth.uniform_residues(ga, (), ctx.q, N))
+        e = torch.from_numpy(synth.small_error(ge, N).astype(np.int32)).cuda()
+        m = torch.from_numpy(np.remainder(polys[k], synth.T_PLAIN).astype(np.int64)).cuda()
+        he.he_encrypt(ctx.h, ds, m, a, e, ct_in[k])
+    dw = torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda()
+    return dict(ctx=ctx, plan=plan, info=info, ct_in=ct_in, w=dw, x=x, wh=w, N=N, L=L,
+                config=dict(workload="conv2d forward, batch 16 x 3x32x32 -> 16 channels, 3x3 kernel, stride 1, pad 1; "
+                                     "N=8192, 3 primes of 50 bits, t=65537; 256 CPMul-accumulates per step",
+                            batch=B, in_channels=C, out_channels=M, map=[H, W], kernel=h, pad=P, N=N, L=L,
+                            cpmul_per_step=info["n_terms"]))
+
+
+def time_path(he, torch, wl, flags, steps, warmup, profile=False):
+    ctx, plan = wl["ctx"], wl["plan"]
+    out = he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"]))
+    ws = he.workspace(plan.workspace_size(flags))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        he.he_corr_conv2d(ctx.h, plan.h, wl["ct_in"], wl["w"], out, flags, ws, ws.numel(), stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if profile:
+        he.he_ctx_profile(ctx.h, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = None
+    if profile:
+        he.he_ctx_profile(ctx.h, False)
+        stats = he.he_ctx_profile_read(ctx.h)
+    return (t1 - t0) / steps, stats, out
+
+
+def time_batched(he, torch, wl, steps, warmup):
+    """The persistent fused kernel (one launch per step, replayed from a HIP graph)."""
+    ctx, plan = wl["ctx"], wl["plan"]
+    out = he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"]))
+    b = he.he_batch_create(0)
+    he.he_batch_add(b, ctx.h, plan.h, wl["ct_in"], wl["w"], out, 0)
+    he.he_batch_build(b, he.HE_BATCH_GRAPH)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        he.he_batch_run(b, stream)
+    he.he_batch_sync(b, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, z in ev:
+        a.record(stream)
+        he.he_batch_run(b, stream)
+        z.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    he.he_batch_sync(b, stream)
+    kern_ms = [a.elapsed_time(z) for a, z in ev]
+    info = he.he_batch_get_info(b)
+    return (t1 - t0) / steps, sum(kern_ms) / len(kern_ms), out, b, info
+
+
+def ntt_rate(he, torch, wl, iters=20):
+    ctx = wl["ctx"]
+    n_polys = 512
+    d = he.empty_u64((n_polys, wl["L"], wl["N"]))
+    d.view(torch.int64).zero_()
+    for _ in range(3):
+        he.he_ntt_fwd(ctx.h, d, n_polys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        he.he_ntt_fwd(ctx.h, d, n_polys)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    return n_polys * wl["L"] / dt
+
+
+def roofline(wl, stats):
+    """Roofline of the dominant kernel: the fused multiply-accumulate + inverse transform."""
+    info, N, L = wl["info"], wl["N"], wl["L"]
+    k = stats["mac_inv"]
+    avg_s = k["total_ms"] / k["launches"] / 1e3
+    planes = info["n_ct_out"] * 2 * L
+    terms_per_plane = info["n_terms"] / info["n_ct_out"]
+    logn = N.bit_length() - 1
+    ops = planes * (terms_per_plane * N * OPS_MAC_TERM + (N // 2) * logn * OPS_BFLY + (N // 2) * OPS_MODMUL)
+    bytes_ = 8 * N * (info["n_ct_in"] * 2 * L + info["n_pt"] * L + planes)
+    alu = ops / avg_s / 1e12
+    hbm = bytes_ / avg_s / 1e9
+    return {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "T VALU-op/s",
+            "frac": round(alu / PEAK_VALU_TOPS, 4), "traffic": None, "kernel": "k_mac_inv (fused MAC + inverse NTT)",
+            "kernel_avg_us": round(avg_s * 1e6, 2), "ops_per_launch": int(ops), "alg_bytes_per_launch": int(bytes_),
+            "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
+
+
+def roofline_persistent(wl, kern_ms, binfo):
+    """Roofline of the persistent kernel, which runs the whole step: forward transforms of
+    inputs and packed plaintexts, multiply-accumulate, inverse transforms."""
+    info, N, L = wl["info"], wl["N"], wl["L"]
+    logn = N.bit_length() - 1
+    avg_s = kern_ms / 1e3
+    bfly = (N // 2) * logn
+    ops = (binfo["fwd_planes"] * bfly * OPS_BFLY
+           + binfo["inv_planes"] * (bfly * OPS_BFLY + (N // 2) * OPS_MODMUL)
+           + info["n_terms"] * 2 * L * N * OPS_MAC_TERM)
+    bytes_ = 8 * N * (info["n_ct_in"] * 2 * L + info["n_ct_out"] * 2 * L) + 4 * 16 * 3 * 9
+    alu = ops / avg_s / 1e12
+    hbm = bytes_ / avg_s / 1e9
+    return {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "T VALU-op/s",
+            "frac": round(alu / PEAK_VALU_TOPS, 4), "traffic": None,
+            "kernel": "k_persistent (whole step: transforms, packing, MAC, inverse transforms)",
+            "kernel_avg_us": round(avg_s * 1e6, 2), "ops_per_launch": int(ops), "alg_bytes_per_launch": int(bytes_),
+            "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
+
+
+def cpu_baseline(wl, he):
+    """The oracle (C, one transform per input plane, OpenMP over planes) on the same batch."""
+    import numpy as np
+    from oracle import core, packing
+    ctx, info = wl["ctx"], wl["info"]
+    g = packing.ConvGeometry(3, 32, 32, 3, 1, wl["N"])
+    ct = he.to_numpy_u64(wl["ct_in"])
+    pt = core.lift(packing.pack_conv_weight(wl["wh"], g).reshape(-1, wl["N"]), ctx.q)
+    row, cti, pti = packing.conv_terms(16, 16, g.cb)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        core.csr_cpmul(ct, pt, row, cti, pti, ctx.q, ctx.psi, method=2)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= 10.0 or reps >= 200:
+            break
+    return {"value": round(reps * info["n_terms"] / dt, 2), "unit": "CPMul-acc/s", "cores": core.num_threads(),
+            "kind": "oracle", "sample": "the full step (256 CPMul-accumulates, batch 16) repeated %d times, %.1f s"
+            % (reps, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        return 2
+    import torch
+    from paper_2409_16675_amd import he, synth
+    wl = workload(he, synth, torch)
+    n_cpmul = wl["info"]["n_terms"]
+    plain_dt, _, out_plain = time_path(he, torch, wl, he.HE_UNFUSED, max(5, args.steps // 2), args.warmup)
+    fused_dt, stats, out_fused = time_path(he, torch, wl, 0, max(5, args.steps // 2), args.warmup, profile=True)
+    dt, kern_ms, out, batch, binfo = time_batched(he, torch, wl, args.steps, args.warmup)
+    same = bool(torch.equal(out.view(torch.int64), out_plain.view(torch.int64)) and
+                torch.equal(out_fused.view(torch.int64), out_plain.view(torch.int64)))
+    res = {
+        "metric": METRIC, "value": round(n_cpmul / dt, 1), "unit": "CPMul-acc/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
+        "path": "batched (persistent fused kernel, graph replay)",
+        "plain_value": round(n_cpmul / plain_dt, 1), "plain_ms_per_step": round(plain_dt * 1e3, 4),
+        "fused_value": round(n_cpmul / fused_dt, 1), "fused_ms_per_step": round(fused_dt * 1e3, 4),
+        "batched_equals_fused_equals_plain": same,
+        "ntt_per_s": round(ntt_rate(he, torch, wl), 1),
+        "kernels_fused_path": {k: dict(v, avg_us=round(v["total_ms"] * 1e3 / v["launches"], 2))
+                               for k, v in stats.items()},
+        "roofline": roofline_persistent(wl, kern_ms, binfo),
+        "roofline_fused_mac_inv": roofline(wl, stats),
+    }
+    he.he_batch_destroy(batch)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(wl, he)
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

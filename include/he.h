@@ -210,6 +210,68 @@ he_status he_encrypt(he_ctx *ctx, const int8_t *s, const int64_t *m, const uint6
  * Synchronises `stream`.  Allocates temporary device memory. */
 he_status he_decrypt(he_ctx *ctx, const int8_t *s, const uint64_t *ct, uint32_t n_ct, int64_t *m, void *stream);
 
+/* ------------------------------------------------------------------ batching */
+/* Many layers (of possibly different ring degrees and shapes) in one persistent
+ * fused kernel: forward transforms of every job's inputs and packed plaintexts,
+ * then per output the multiply-accumulate and inverse transform, drained from a
+ * device task table by one workgroup per compute unit, with per-job completion
+ * counters ordering each job's phases.  The launch is captured into a HIP graph
+ * at build time and replayed by he_batch_run.  Results are byte-identical to
+ * running each job alone with he_corr_conv2d. */
+typedef struct {
+  const he_plan *plan;     /* the job's layer plan (its context fixes N, L) */
+  const uint64_t *ct_in;   /* device [n_ct_in][2][L][N], coefficient form (transformed if HE_IN_NTT) */
+  const void *plain;       /* device: raw int32 weights (CONV, FC) or int64 polynomials (HE_PLAIN_POLY) */
+  uint64_t *ct_out;        /* device [n_ct_out][2][L][N], coefficient form */
+  uint32_t flags;          /* HE_IN_NTT, HE_PLAIN_POLY, HE_ACCUMULATE */
+  uint32_t reserved;
+} he_job;
+
+typedef struct {
+  uint32_t n_jobs, n_tasks, grid, arith;
+  uint64_t cpmul;          /* CPMul-accumulates per run */
+  uint64_t fwd_planes;     /* forward plane transforms per run */
+  uint64_t inv_planes;     /* inverse plane transforms per run */
+  uint64_t ws_bytes;       /* device workspace owned by the batch */
+} he_batch_info;
+
+#define HE_BATCH_GRAPH 0x1u    /* capture the launch into a HIP graph (default on) */
+
+/* Create an empty batch for `device` (host memory only). */
+he_status he_batch_create(int32_t device, he_batch **out);
+/* Append a job; the plan and every buffer must stay valid while the batch is used.
+ * All jobs of a batch must use the same arithmetic (all primes < 2^50, or not). */
+he_status he_batch_add(he_batch *b, he_ctx *ctx, const he_job *job, uint32_t *index);
+/* Plan the task table, allocate the batch workspace and device tables, and
+ * (with HE_BATCH_GRAPH) capture the launch into a graph.  Allocates device memory. */
+he_status he_batch_build(he_batch *b, uint32_t flags);
+/* Point job `index` at new buffers (same plan); no re-capture is needed. */
+he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job);
+/* Launch the whole batch on `stream` (asynchronous). */
+he_status he_batch_run(he_batch *b, void *stream);
+/* Wait for `stream` and report HE_ETIMEOUT if a dependency wait hit its bound. */
+he_status he_batch_sync(he_batch *b, void *stream);
+he_status he_batch_get_info(const he_batch *b, he_batch_info *info);
+he_status he_batch_destroy(he_batch *b);
+
+/* ------------------------------------------------------------ kernel timing */
+/* Per-kernel timing on the launch stream: while enabled, every kernel the
+ * context's calls launch is bracketed by two HIP events on the stream it is
+ * launched on.  he_ctx_profile(ctx, 1) clears and starts, (ctx, 0) stops;
+ * he_ctx_profile_read waits for the recorded events and returns one entry per
+ * kernel kind (at most cap entries).  Kinds: 0 forward transform, 1 forward
+ * transform of packed plaintexts, 2 inverse transform, 3 fused multiply-
+ * accumulate + inverse transform, 4 multiply-accumulate in the transformed
+ * domain, 5 packing, 6 persistent batch kernel. */
+typedef struct {
+  uint32_t kind;
+  uint32_t launches;
+  double total_ms;
+  double max_ms;
+} he_kernel_stat;
+he_status he_ctx_profile(he_ctx *ctx, int enable);
+he_status he_ctx_profile_read(he_ctx *ctx, he_kernel_stat *out, uint32_t cap, uint32_t *n);
+
 /* ------------------------------------------------------------------ errors */
 const char *he_status_str(he_status status);
 const char *he_last_error(void);

@@ -1,0 +1,277 @@
+// Batch runtime: task-table planning, workspace, graph capture and replay for
+// the persistent fused kernel.
+#include <algorithm>
+
+#include "batch.hpp"
+#include "plan.hpp"
+
+namespace he {
+struct BJob {
+  Ctx *ctx;
+  const Plan *plan;
+  he_job job;
+};
+}  // namespace he
+
+struct he_batch {
+  int device = 0;
+  std::vector<he::BJob> jobs;
+  bool built = false;
+  int arith = HE_ARITH_F64;
+  void *d_ws = nullptr;
+  size_t ws_bytes = 0;
+  he::PTask *d_tasks = nullptr;
+  he::PJob *d_jobs = nullptr;
+  uint32_t *d_ctl = nullptr;
+  uint32_t n_tasks = 0, ctl_words = 0, grid = 0;
+  std::vector<he::PJob> h_jobs;
+  std::vector<size_t> ct_hat_off, pt_hat_off;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  he_batch_info info{};
+  uint32_t spin_limit = 1u << 24;
+};
+
+using namespace he;
+
+static inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static void release(he_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (void *p : {b->d_ws, (void *)b->d_tasks, (void *)b->d_jobs, (void *)b->d_ctl})
+    if (p) (void)hipFree(p);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->cap = nullptr;
+  b->d_ws = nullptr;
+  b->d_tasks = nullptr;
+  b->d_jobs = nullptr;
+  b->d_ctl = nullptr;
+  b->built = false;
+}
+
+static he_status fill_job(const he_batch *b, uint32_t idx, PJob &pj) {
+  const BJob &bj = b->jobs[idx];
+  const Ctx &c = *bj.ctx;
+  const Plan &p = *bj.plan;
+  const he_plan_info &in = p.info;
+  const uint32_t f = bj.job.flags;
+  pj = PJob{};
+  pj.primes = c.d_primes;
+  pj.tw_fwd = b->arith == HE_ARITH_F64 ? c.d_tw_f64_fwd : c.d_tw_u64_fwd;
+  pj.tw_inv = b->arith == HE_ARITH_F64 ? c.d_tw_f64_inv : c.d_tw_u64_inv;
+  pj.ct_in = bj.job.ct_in;
+  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in) : (uint64_t *)((char *)b->d_ws + b->ct_hat_off[idx]);
+  pj.plain = bj.job.plain;
+  pj.pt_hat = (uint64_t *)((char *)b->d_ws + b->pt_hat_off[idx]);
+  pj.ct_out = bj.job.ct_out;
+  pj.row = p.d_row();
+  pj.cti = p.d_cti();
+  pj.pti = p.d_pti();
+  pj.logN = c.logN;
+  pj.L = c.L;
+  pj.accumulate = (f & HE_ACCUMULATE) ? 1u : 0u;
+  pj.pkind = (f & HE_PLAIN_POLY) ? PK_POLY : (in.kind == HE_KIND_FC ? PK_FC : PK_CONV);
+  if (in.kind == HE_KIND_DW && pj.pkind != PK_POLY) return fail(HE_EUNSUPPORTED, "weight-gradient jobs need HE_PLAIN_POLY");
+  pj.M = p.shape.M;
+  pj.C = p.shape.C;
+  pj.h = p.shape.h;
+  pj.O = in.O;
+  pj.S = in.S;
+  pj.Cw = in.Cw;
+  pj.cb = in.cb;
+  pj.n_in = p.shape.n_in;
+  pj.n_out = p.shape.n_out;
+  pj.n_iw = in.n_iw;
+  pj.n_ow = in.n_ow;
+  pj.in_ct = in.n_iw ? (p.shape.n_in + in.n_iw - 1) / in.n_iw : 0;
+  return HE_OK;
+}
+
+extern "C" {
+
+he_status he_batch_create(int32_t device, he_batch **out) {
+  if (!out) return fail(HE_EINVAL, "null output");
+  *out = new he_batch();
+  (*out)->device = device;
+  return HE_OK;
+}
+
+he_status he_batch_add(he_batch *b, he_ctx *ctx, const he_job *job, uint32_t *index) {
+  if (!b || !ctx || !job || !job->plan) return fail(HE_EINVAL, "null argument");
+  if (b->built) return fail(HE_EINVAL, "batch already built");
+  if (job->plan->ctx != ctx->c) return fail(HE_EINVAL, "plan belongs to another context");
+  if (!job->ct_in || !job->plain || !job->ct_out) return fail(HE_EINVAL, "null job buffer");
+  if (ctx->c->device != b->device) return fail(HE_EINVAL, "context on another device");
+  if (ctx->c->logN < 10 || ctx->c->logN > 14) return fail(HE_EUNSUPPORTED, "ring degree");
+  b->jobs.push_back(BJob{ctx->c, &job->plan->p, *job});
+  if (index) *index = (uint32_t)(b->jobs.size() - 1);
+  return HE_OK;
+}
+
+he_status he_batch_build(he_batch *b, uint32_t flags) {
+  if (!b) return fail(HE_EINVAL, "null batch");
+  release(b);
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  bool all_f64 = true;
+  for (auto &j : b->jobs) all_f64 = all_f64 && j.ctx->f64_ok;
+  b->arith = all_f64 ? HE_ARITH_F64 : HE_ARITH_U64;
+  // workspace: transformed inputs and plaintexts per job
+  const size_t nj = b->jobs.size();
+  b->ct_hat_off.assign(nj, 0);
+  b->pt_hat_off.assign(nj, 0);
+  size_t off = 0;
+  he_batch_info info{};
+  for (size_t j = 0; j < nj; ++j) {
+    const BJob &bj = b->jobs[j];
+    const he_plan_info &in = bj.plan->info;
+    const size_t plane = (size_t)bj.ctx->L * bj.ctx->N * 8;
+    if (!(bj.job.flags & HE_IN_NTT)) {
+      b->ct_hat_off[j] = off;
+      off += al256((size_t)in.n_ct_in * 2 * plane);
+    }
+    b->pt_hat_off[j] = off;
+    off += al256((size_t)in.n_pt * plane);
+    info.cpmul += in.n_terms;
+  }
+  b->ws_bytes = off;
+  if (off && (e = hipMalloc(&b->d_ws, off)) != hipSuccess) {
+    release(b);
+    return hip_fail(e, "batch workspace");
+  }
+  // task table: every job's pre tasks, then every job's multiply-accumulate tasks
+  std::vector<PTask> tasks;
+  std::vector<PJob> pjobs(nj);
+  for (size_t j = 0; j < nj; ++j) {
+    he_status s = fill_job(b, (uint32_t)j, pjobs[j]);
+    if (s != HE_OK) {
+      release(b);
+      return s;
+    }
+    const BJob &bj = b->jobs[j];
+    const he_plan_info &in = bj.plan->info;
+    const uint32_t G = 16384u >> bj.ctx->logN, L = bj.ctx->L;
+    const size_t before = tasks.size();
+    if (!(bj.job.flags & HE_IN_NTT)) {
+      const uint32_t planes = in.n_ct_in * 2 * L;
+      for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p)});
+      info.fwd_planes += planes;
+    }
+    const uint32_t pplanes = in.n_pt * L;
+    for (uint32_t p = 0; p < pplanes; p += G) tasks.push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p)});
+    info.fwd_planes += pplanes;
+    pjobs[j].n_pre = (uint32_t)(tasks.size() - before);
+  }
+  for (size_t j = 0; j < nj; ++j) {
+    const BJob &bj = b->jobs[j];
+    const uint32_t G = 16384u >> bj.ctx->logN;
+    const uint32_t planes = bj.plan->info.n_ct_out * 2 * bj.ctx->L;
+    for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
+    info.inv_planes += planes;
+  }
+  b->h_jobs = pjobs;
+  b->n_tasks = (uint32_t)tasks.size();
+  b->ctl_words = CTL_DONE + (uint32_t)nj;
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) {
+    release(b);
+    return hip_fail(e, "device attribute");
+  }
+  b->grid = (uint32_t)std::max(1, std::min<int>(cus, (int)std::max<uint32_t>(1u, b->n_tasks)));
+  if ((e = hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(PTask))) != hipSuccess ||
+      (e = hipMalloc(&b->d_jobs, std::max<size_t>(1, nj) * sizeof(PJob))) != hipSuccess ||
+      (e = hipMalloc(&b->d_ctl, b->ctl_words * 4)) != hipSuccess ||
+      (tasks.size() && (e = hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(PTask), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (nj && (e = hipMemcpy(b->d_jobs, pjobs.data(), nj * sizeof(PJob), hipMemcpyHostToDevice)) != hipSuccess)) {
+    release(b);
+    return hip_fail(e, "batch tables");
+  }
+  info.n_jobs = (uint32_t)nj;
+  info.n_tasks = b->n_tasks;
+  info.grid = b->grid;
+  info.arith = (uint32_t)b->arith;
+  info.ws_bytes = b->ws_bytes;
+  b->info = info;
+  if (flags & HE_BATCH_GRAPH) {
+    if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+      release(b);
+      return hip_fail(e, "graph capture");
+    }
+    hipError_t le = launch_persistent(b->arith, b->d_tasks, b->n_tasks, b->d_jobs, b->d_ctl, b->ctl_words, b->grid,
+                                      b->spin_limit, b->cap);
+    e = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess || e != hipSuccess ||
+        (e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+      release(b);
+      return hip_fail(le != hipSuccess ? le : e, "graph build");
+    }
+  }
+  b->built = true;
+  return HE_OK;
+}
+
+he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job) {
+  if (!b || !job) return fail(HE_EINVAL, "null argument");
+  if (index >= b->jobs.size()) return fail(HE_EINVAL, "job index");
+  BJob &bj = b->jobs[index];
+  if (job->plan != nullptr && &job->plan->p != bj.plan) return fail(HE_EINVAL, "rebind must keep the plan");
+  const uint32_t keep = HE_IN_NTT | HE_PLAIN_POLY;
+  if ((job->flags & keep) != (bj.job.flags & keep)) return fail(HE_EINVAL, "rebind must keep the input flags");
+  he_job nj = *job;
+  nj.plan = bj.job.plan;
+  bj.job = nj;
+  if (!b->built) return HE_OK;
+  PJob pj;
+  he_status s = fill_job(b, index, pj);
+  if (s != HE_OK) return s;
+  pj.n_pre = b->h_jobs[index].n_pre;
+  b->h_jobs[index] = pj;
+  hipError_t e = hipMemcpy(b->d_jobs + index, &pj, sizeof(PJob), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "rebind");
+  return HE_OK;
+}
+
+he_status he_batch_run(he_batch *b, void *stream) {
+  if (!b || !b->built) return fail(HE_EINVAL, "batch not built");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (b->exec) e = hipGraphLaunch(b->exec, st);
+  else e = launch_persistent(b->arith, b->d_tasks, b->n_tasks, b->d_jobs, b->d_ctl, b->ctl_words, b->grid,
+                             b->spin_limit, st);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  return HE_OK;
+}
+
+he_status he_batch_sync(he_batch *b, void *stream) {
+  if (!b || !b->built) return fail(HE_EINVAL, "batch not built");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "batch sync");
+  uint32_t err = 0;
+  e = hipMemcpy(&err, b->d_ctl + CTL_ERR, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "batch status");
+  if (err) return fail(HE_ETIMEOUT, "a dependency wait in the persistent kernel hit its bound");
+  return HE_OK;
+}
+
+he_status he_batch_get_info(const he_batch *b, he_batch_info *info) {
+  if (!b || !info) return fail(HE_EINVAL, "null argument");
+  *info = b->info;
+  info->n_jobs = (uint32_t)b->jobs.size();
+  return HE_OK;
+}
+
+he_status he_batch_destroy(he_batch *b) {
+  if (!b) return HE_OK;
+  (void)hipSetDevice(b->device);
+  release(b);
+  delete b;
+  return HE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Device-visible job and task descriptors of the persistent batch kernel.
+#pragma once
+#include "he_internal.hpp"
+
+namespace he {
+
+enum PTaskKind : uint32_t { PT_FWD_CT = 0, PT_PT = 1, PT_MAC_INV = 2 };
+enum PlainKind : uint32_t { PK_CONV = 0, PK_FC = 1, PK_POLY = 2 };
+
+// control words: queue head, error flag, then one completion counter per job
+enum : uint32_t { CTL_HEAD = 0, CTL_ERR = 1, CTL_DONE = 64 };
+
+struct PTask {
+  uint32_t kind, job, first, count;   // planes [first, first + count) of the job's array
+};
+
+struct PJob {
+  const PrimeK *primes;
+  const void *tw_fwd, *tw_inv;
+  const uint64_t *ct_in;
+  uint64_t *ct_hat;      // == ct_in when the inputs are already transformed
+  const void *plain;
+  uint64_t *pt_hat;
+  uint64_t *ct_out;
+  const int32_t *row, *cti, *pti;
+  uint32_t logN, L, n_pre, accumulate;
+  uint32_t pkind;
+  uint32_t M, C, h, O, S, Cw, cb;
+  uint32_t n_in, n_out, n_iw, n_ow, in_ct;
+  uint32_t pad_;
+};
+
+size_t persistent_lds_bytes();
+hipError_t launch_persistent(int arith, const PTask *tasks, uint32_t n_tasks, const PJob *jobs, uint32_t *ctl,
+                             uint32_t ctl_words, uint32_t grid, uint32_t spin_limit, hipStream_t st);
+
+}  // namespace he

@@ -59,8 +59,11 @@ he_status he_ctx_create(const he_params *params, he_ctx **out) {
   return HE_OK;
 }
 
+static void prof_clear(const Ctx &c);
+
 he_status he_ctx_destroy(he_ctx *ctx) {
   if (!ctx) return HE_OK;
+  prof_clear(*ctx->c);
   free_context(ctx->c);
   delete ctx;
   return HE_OK;
@@ -109,17 +112,62 @@ he_status he_ctx_get_schedule(const he_ctx *ctx, uint32_t op, uint32_t *arith, u
   return HE_OK;
 }
 
+static void prof_clear(const Ctx &c) {
+  std::lock_guard<std::mutex> g(c.prof_mu);
+  for (auto &r : c.prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c.prof.clear();
+}
+
+he_status he_ctx_profile(he_ctx *ctx, int enable) {
+  if (!ctx) return fail(HE_EINVAL, "null context");
+  if (enable) prof_clear(*ctx->c);
+  ctx->c->prof_on = enable != 0;
+  return HE_OK;
+}
+
+he_status he_ctx_profile_read(he_ctx *ctx, he_kernel_stat *out, uint32_t cap, uint32_t *n) {
+  if (!ctx || !n) return fail(HE_EINVAL, "null argument");
+  const Ctx &c = *ctx->c;
+  he_kernel_stat acc[8];
+  for (uint32_t k = 0; k < 8; ++k) acc[k] = he_kernel_stat{k, 0, 0.0, 0.0};
+  {
+    std::lock_guard<std::mutex> g(c.prof_mu);
+    for (auto &r : c.prof) {
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e != hipSuccess) return hip_fail(e, "profile sync");
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess) return hip_fail(e, "profile elapsed");
+      he_kernel_stat &s = acc[r.kind & 7];
+      s.launches++;
+      s.total_ms += ms;
+      if (ms > s.max_ms) s.max_ms = ms;
+    }
+  }
+  uint32_t m = 0;
+  for (uint32_t k = 0; k < 8; ++k)
+    if (acc[k].launches) {
+      if (out && m < cap) out[m] = acc[k];
+      ++m;
+    }
+  *n = m < cap ? m : cap;
+  return HE_OK;
+}
+
 he_status he_ntt_fwd(he_ctx *ctx, uint64_t *planes, uint32_t n_polys, void *stream) {
   if (!ctx || (!planes && n_polys)) return fail(HE_EINVAL, "null argument");
   const Ctx &c = *ctx->c;
-  HIPCHK(launch_ntt_fwd(c, c.s_fwd, planes, planes, n_polys * c.L, (hipStream_t)stream), "ntt_fwd launch");
+  HIPCHK(timed(c, (hipStream_t)stream, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, planes, planes, n_polys * c.L, (hipStream_t)stream); }), "ntt_fwd launch");
   return HE_OK;
 }
 
 he_status he_ntt_inv(he_ctx *ctx, uint64_t *planes, uint32_t n_polys, void *stream) {
   if (!ctx || (!planes && n_polys)) return fail(HE_EINVAL, "null argument");
   const Ctx &c = *ctx->c;
-  HIPCHK(launch_ntt_inv(c, c.s_inv, planes, planes, n_polys * c.L, (hipStream_t)stream), "ntt_inv launch");
+  HIPCHK(timed(c, (hipStream_t)stream, KK_INV, [&] { return launch_ntt_inv(c, c.s_inv, planes, planes, n_polys * c.L, (hipStream_t)stream); }), "ntt_inv launch");
   return HE_OK;
 }
 
@@ -163,15 +211,15 @@ he_status he_cpmul_acc(he_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint
   if (!(flags & HE_IN_NTT)) {
     uint64_t *a = (uint64_t *)w;
     uint64_t *b = (uint64_t *)(w + al256((size_t)K * 2 * c.L * c.N * 8));
-    HIPCHK(launch_ntt_fwd(c, c.s_fwd, a, ct, K * 2 * c.L, st), "cpmul fwd ct");
-    HIPCHK(launch_ntt_fwd(c, c.s_fwd, b, pt, K * c.L, st), "cpmul fwd pt");
+    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, a, ct, K * 2 * c.L, st); }), "cpmul fwd ct");
+    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, b, pt, K * c.L, st); }), "cpmul fwd pt");
     ct_hat = a;
     pt_hat = b;
   }
   Terms tm;
   tm.n_out = 1;
   tm.K = K;
-  HIPCHK(launch_mac(c, c.s_mac, acc, ct_hat, pt_hat, tm, (flags & HE_ACCUMULATE) != 0, (flags & HE_OUT_NTT) != 0, st),
+  HIPCHK(timed(c, st, (flags & HE_OUT_NTT) ? KK_MAC : KK_MAC_INV, [&] { return launch_mac(c, c.s_mac, acc, ct_hat, pt_hat, tm, (flags & HE_ACCUMULATE) != 0, (flags & HE_OUT_NTT) != 0, st); }),
          "cpmul mac");
   return HE_OK;
 }
@@ -283,26 +331,27 @@ he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in
   const uint64_t *ct_hat = ct_in;
   if (!(flags & HE_IN_NTT)) {
     uint64_t *d = (uint64_t *)(w + L.ct_hat);
-    HIPCHK(launch_ntt_fwd(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, st), "conv fwd ct");
+    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, st); }), "conv fwd ct");
     ct_hat = d;
   }
   // 2. pack (raw weights) and transform the plaintexts
   const int64_t *polys = (const int64_t *)plain;
   if (!(flags & HE_PLAIN_POLY)) {
     int64_t *pp = (int64_t *)(w + L.pt_poly);
-    HIPCHK(launch_zero_i64(pp, (size_t)in.n_pt * c.N, st), "conv zero");
-    if (in.kind == HE_KIND_CONV)
-      HIPCHK(launch_pack_conv_w(pp, (const int32_t *)plain, p.shape.M, p.shape.C, p.shape.h, in.O, in.S, in.Cw, in.cb,
-                                c.N, st),
-             "conv pack");
-    else
-      HIPCHK(launch_pack_fc_w(pp, (const int32_t *)plain, p.shape.n_out, p.shape.n_in, in.n_iw, in.n_ow,
-                              (p.shape.n_in + in.n_iw - 1) / in.n_iw, c.N, st),
-             "fc pack");
+    HIPCHK(timed(c, st, KK_PACK, [&] {
+             hipError_t e = launch_zero_i64(pp, (size_t)in.n_pt * c.N, st);
+             if (e != hipSuccess) return e;
+             if (in.kind == HE_KIND_CONV)
+               return launch_pack_conv_w(pp, (const int32_t *)plain, p.shape.M, p.shape.C, p.shape.h, in.O, in.S,
+                                         in.Cw, in.cb, c.N, st);
+             return launch_pack_fc_w(pp, (const int32_t *)plain, p.shape.n_out, p.shape.n_in, in.n_iw, in.n_ow,
+                                     (p.shape.n_in + in.n_iw - 1) / in.n_iw, c.N, st);
+           }),
+           "pack");
     polys = pp;
   }
   uint64_t *pt_hat = (uint64_t *)(w + L.pt_hat);
-  HIPCHK(launch_ntt_fwd_lift(c, c.s_fwd, pt_hat, polys, in.n_pt, st), "conv fwd pt");
+  HIPCHK(timed(c, st, KK_FWD_LIFT, [&] { return launch_ntt_fwd_lift(c, c.s_fwd, pt_hat, polys, in.n_pt, st); }), "conv fwd pt");
   // 3. multiply-accumulate + inverse transform
   Terms tm;
   tm.row = p.d_row();
@@ -311,18 +360,18 @@ he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in
   tm.n_out = in.n_ct_out;
   const bool accum = (flags & HE_ACCUMULATE) != 0;
   if (flags & HE_OUT_NTT) {
-    HIPCHK(launch_mac(c, c.s_mac, ct_out, ct_hat, pt_hat, tm, accum, true, st), "conv mac");
+    HIPCHK(timed(c, st, KK_MAC, [&] { return launch_mac(c, c.s_mac, ct_out, ct_hat, pt_hat, tm, accum, true, st); }), "conv mac");
   } else if (flags & HE_UNFUSED) {
     uint64_t *acc = (uint64_t *)(w + L.acc);
-    HIPCHK(launch_mac(c, c.s_mac, acc, ct_hat, pt_hat, tm, false, true, st), "conv mac");
+    HIPCHK(timed(c, st, KK_MAC, [&] { return launch_mac(c, c.s_mac, acc, ct_hat, pt_hat, tm, false, true, st); }), "conv mac");
     if (accum) {
-      HIPCHK(launch_ntt_inv(c, c.s_inv, acc, acc, in.n_ct_out * 2 * c.L, st), "conv inv");
+      HIPCHK(timed(c, st, KK_INV, [&] { return launch_ntt_inv(c, c.s_inv, acc, acc, in.n_ct_out * 2 * c.L, st); }), "conv inv");
       HIPCHK(launch_add_planes(c, ct_out, ct_out, acc, in.n_ct_out * 2 * c.L, st), "conv add");
     } else {
-      HIPCHK(launch_ntt_inv(c, c.s_inv, ct_out, acc, in.n_ct_out * 2 * c.L, st), "conv inv");
+      HIPCHK(timed(c, st, KK_INV, [&] { return launch_ntt_inv(c, c.s_inv, ct_out, acc, in.n_ct_out * 2 * c.L, st); }), "conv inv");
     }
   } else {
-    HIPCHK(launch_mac(c, c.s_mac, ct_out, ct_hat, pt_hat, tm, accum, false, st), "conv mac+inv");
+    HIPCHK(timed(c, st, KK_MAC_INV, [&] { return launch_mac(c, c.s_mac, ct_out, ct_hat, pt_hat, tm, accum, false, st); }), "conv mac+inv");
   }
   return HE_OK;
 }

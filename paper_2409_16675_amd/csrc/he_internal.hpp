@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,9 +32,37 @@ struct Ctx {
   void *d_tw_f64_inv = nullptr;
   void *d_tw_u64_fwd = nullptr;      // TwU64 [L][N]
   void *d_tw_u64_inv = nullptr;
+  // per-kernel timing (he_ctx_profile)
+  struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  mutable std::mutex prof_mu;
+  mutable bool prof_on = false;
+  mutable std::vector<ProfRec> prof;
   // schedules chosen per operation (autotuner may change them)
   Sched s_fwd{HE_ARITH_U64, 4}, s_inv{HE_ARITH_U64, 4}, s_mac{HE_ARITH_U64, 4};
 };
+
+enum KernelKind { KK_FWD = 0, KK_FWD_LIFT = 1, KK_INV = 2, KK_MAC_INV = 3, KK_MAC = 4, KK_PACK = 5, KK_PERSIST = 6 };
+
+// Bracket one launch with events when profiling is on: returns the launch's error.
+template <class F>
+hipError_t timed(const Ctx &c, hipStream_t st, int kind, F &&launch) {
+  if (!c.prof_on) return launch();
+  Ctx::ProfRec r{kind, nullptr, nullptr};
+  hipError_t e = hipEventCreate(&r.a);
+  if (e == hipSuccess) e = hipEventCreate(&r.b);
+  if (e == hipSuccess) e = hipEventRecord(r.a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  hipError_t e2 = hipEventRecord(r.b, st);
+  {
+    std::lock_guard<std::mutex> g(c.prof_mu);
+    c.prof.push_back(r);
+  }
+  return e != hipSuccess ? e : e2;
+}
 
 // thread-local error text
 void set_error(const std::string &msg);

@@ -55,6 +55,8 @@ _SIGS = {
                     ctypes.POINTER(c_u32)],
     "he_ctx_set_schedule": [c_void_p, c_u32, c_u32, c_u32],
     "he_ctx_get_schedule": [c_void_p, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
+    "he_ctx_profile": [c_void_p, ctypes.c_int],
+    "he_ctx_profile_read": [c_void_p, c_void_p, c_u32, ctypes.POINTER(c_u32)],
     "he_ntt_fwd": [c_void_p, c_void_p, c_u32, c_void_p],
     "he_ntt_inv": [c_void_p, c_void_p, c_u32, c_void_p],
     "he_cpmul_acc": [c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_u32, c_void_p, c_size, c_void_p],
@@ -69,6 +71,14 @@ _SIGS = {
     "he_extract_output": [c_void_p, i64p, i64p],
     "he_encrypt": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "he_decrypt": [c_void_p, c_void_p, c_void_p, c_u32, i64p, c_void_p],
+    "he_batch_create": [c_i32, ctypes.POINTER(c_void_p)],
+    "he_batch_add": [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_u32)],
+    "he_batch_build": [c_void_p, c_u32],
+    "he_batch_rebind": [c_void_p, c_u32, c_void_p],
+    "he_batch_run": [c_void_p, c_void_p],
+    "he_batch_sync": [c_void_p, c_void_p],
+    "he_batch_get_info": [c_void_p, c_void_p],
+    "he_batch_destroy": [c_void_p],
 }
 for _n, _a in _SIGS.items():
     _f = getattr(_lib, _n)
@@ -172,6 +182,25 @@ def compiled_schedules(N, f64_ok=True):
     return out
 
 
+class he_kernel_stat(ctypes.Structure):
+    _fields_ = [("kind", c_u32), ("launches", c_u32), ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
+KERNEL_KINDS = {0: "ntt_fwd", 1: "ntt_fwd_lift", 2: "ntt_inv", 3: "mac_inv", 4: "mac", 5: "pack", 6: "persistent"}
+
+
+def he_ctx_profile(ctx, enable):
+    _chk(_lib.he_ctx_profile(ctx, 1 if enable else 0), "he_ctx_profile")
+
+
+def he_ctx_profile_read(ctx):
+    arr = (he_kernel_stat * 8)()
+    n = c_u32()
+    _chk(_lib.he_ctx_profile_read(ctx, ctypes.cast(arr, c_void_p), 8, ctypes.byref(n)), "he_ctx_profile_read")
+    return {KERNEL_KINDS[arr[i].kind]: dict(launches=arr[i].launches, total_ms=arr[i].total_ms, max_ms=arr[i].max_ms)
+            for i in range(n.value)}
+
+
 def he_ntt_fwd(ctx, planes, n_polys, stream=None):
     _chk(_lib.he_ntt_fwd(ctx, _ptr(planes), n_polys, _stream(stream)), "he_ntt_fwd")
 
@@ -253,6 +282,65 @@ def he_decrypt(ctx, s, ct, n_ct, N, stream=None):
     m = np.zeros(n_ct * N, dtype=np.int64)
     _chk(_lib.he_decrypt(ctx, _ptr(s), _ptr(ct), n_ct, m.ctypes.data_as(i64p), _stream(stream)), "he_decrypt")
     return m.reshape(n_ct, N)
+
+
+# ------------------------------------------------------------------ batching
+HE_BATCH_GRAPH = 0x1
+
+
+class he_job(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("ct_in", c_void_p), ("plain", c_void_p), ("ct_out", c_void_p), ("flags", c_u32),
+                ("reserved", c_u32)]
+
+
+class he_batch_info(ctypes.Structure):
+    _fields_ = [("n_jobs", c_u32), ("n_tasks", c_u32), ("grid", c_u32), ("arith", c_u32), ("cpmul", c_u64),
+                ("fwd_planes", c_u64), ("inv_planes", c_u64), ("ws_bytes", c_u64)]
+
+
+def _job(plan, ct_in, plain, ct_out, flags):
+    return he_job(plan.value if isinstance(plan, c_void_p) else plan, _ptr(ct_in).value, _ptr(plain).value,
+                  _ptr(ct_out).value, flags, 0)
+
+
+def he_batch_create(device=0):
+    h = c_void_p()
+    _chk(_lib.he_batch_create(device, ctypes.byref(h)), "he_batch_create")
+    return h
+
+
+def he_batch_add(b, ctx, plan, ct_in, plain, ct_out, flags=0):
+    j = _job(plan, ct_in, plain, ct_out, flags)
+    idx = c_u32()
+    _chk(_lib.he_batch_add(b, ctx, ctypes.byref(j), ctypes.byref(idx)), "he_batch_add")
+    return idx.value
+
+
+def he_batch_build(b, flags=HE_BATCH_GRAPH):
+    _chk(_lib.he_batch_build(b, flags), "he_batch_build")
+
+
+def he_batch_rebind(b, index, plan, ct_in, plain, ct_out, flags=0):
+    j = _job(plan, ct_in, plain, ct_out, flags)
+    _chk(_lib.he_batch_rebind(b, index, ctypes.byref(j)), "he_batch_rebind")
+
+
+def he_batch_run(b, stream=None):
+    _chk(_lib.he_batch_run(b, _stream(stream)), "he_batch_run")
+
+
+def he_batch_sync(b, stream=None):
+    _chk(_lib.he_batch_sync(b, _stream(stream)), "he_batch_sync")
+
+
+def he_batch_get_info(b):
+    i = he_batch_info()
+    _chk(_lib.he_batch_get_info(b, ctypes.byref(i)), "he_batch_get_info")
+    return {n: getattr(i, n) for n, _ in he_batch_info._fields_}
+
+
+def he_batch_destroy(b):
+    _chk(_lib.he_batch_destroy(b), "he_batch_destroy")
 
 
 # ------------------------------------------------------------------ helpers
