@@ -207,6 +207,9 @@ def main():
     from paper_2409_16675_amd import he, synth
     wl = workload(he, synth, torch)
     n_cpmul = wl["info"]["n_terms"]
+    tune = he.he_autotune(wl["ctx"].h, 512)      # set-up: picks the fastest bit-exact schedules
+    chosen = {name: he.he_ctx_get_schedule(wl["ctx"].h, op) for name, op in
+              (("fwd", he.HE_OP_FWD), ("inv", he.HE_OP_INV), ("mac", he.HE_OP_MAC))}
     plain_dt, _, out_plain = time_path(he, torch, wl, he.HE_UNFUSED, max(5, args.steps // 2), args.warmup)
     fused_dt, stats, out_fused = time_path(he, torch, wl, 0, max(5, args.steps // 2), args.warmup, profile=True)
     dt, kern_ms, out, batch, binfo = time_batched(he, torch, wl, args.steps, args.warmup)
@@ -223,6 +226,11 @@ def main():
         "ntt_per_s": round(ntt_rate(he, torch, wl), 1),
         "kernels_fused_path": {k: dict(v, avg_us=round(v["total_ms"] * 1e3 / v["launches"], 2))
                                for k, v in stats.items()},
+        "schedules": {k: {"arith": "f64" if v[0] == 1 else "u64", "coeffs_per_thread": 1 << v[1]}
+                      for k, v in chosen.items()},
+        "autotune_us": ["%s/%s/%d: %.1f%s" % (("fwd", "inv", "mac")[t["op"]], "f64" if t["arith"] == 1 else "u64",
+                                              1 << t["loge"], t["us"], "" if t["exact"] else " (mismatch)")
+                        for t in tune],
         "roofline": roofline_persistent(wl, kern_ms, binfo),
         "roofline_fused_mac_inv": roofline(wl, stats),
     }

@@ -99,6 +99,21 @@ he_status he_ctx_info(const he_ctx *ctx, uint32_t *N, uint32_t *L, uint64_t *t, 
 he_status he_ctx_set_schedule(he_ctx *ctx, uint32_t op, uint32_t arith, uint32_t loge);
 he_status he_ctx_get_schedule(const he_ctx *ctx, uint32_t op, uint32_t *arith, uint32_t *loge);
 
+/* Autotuner: times every compiled schedule of the forward transform, the inverse
+ * transform and the fused multiply-accumulate + inverse kernel on n_polys
+ * polynomials of seeded data, keeps only candidates whose output is identical
+ * to the reference schedule's, and installs the fastest in the context.  With
+ * cache_path, a matching entry (device architecture, N, L, first prime) is read
+ * instead of timing, and a new result is appended as one JSON line.  `report`
+ * (optional, host) receives up to report_cap entries.  Allocates and frees
+ * device memory; synchronises `stream`. */
+typedef struct {
+  uint32_t op, arith, loge, exact;
+  double us;               /* average time per launch */
+} he_tune_entry;
+he_status he_autotune(he_ctx *ctx, uint32_t n_polys, const char *cache_path, void *stream, he_tune_entry *report,
+                      uint32_t report_cap, uint32_t *report_n);
+
 /* ---------------------------------------------------------------- transforms */
 
 /* In-place forward transform of n_polys polynomials, device planes [n_polys][L][N]. */
@@ -235,7 +250,8 @@ typedef struct {
   uint64_t ws_bytes;       /* device workspace owned by the batch */
 } he_batch_info;
 
-#define HE_BATCH_GRAPH 0x1u    /* capture the launch into a HIP graph (default on) */
+#define HE_BATCH_GRAPH 0x1u        /* capture the launch into a HIP graph (default on) */
+#define HE_BATCH_STRICT_SYNC 0x2u  /* every wave fences at every dependency (slower; for checking) */
 
 /* Create an empty batch for `device` (host memory only). */
 he_status he_batch_create(int32_t device, he_batch **out);

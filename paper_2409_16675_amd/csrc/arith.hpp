@@ -60,17 +60,23 @@ struct ArF64 {
 
   __device__ __forceinline__ explicit ArF64(const PrimeK &p) : q(p.qd), qinv(p.qinv) {}
 
-  __device__ __forceinline__ V load(uint64_t x) const { return (double)x; }
+  // x < 2^53: two 32-bit conversions and one FMA (exact)
+  __device__ __forceinline__ V load(uint64_t x) const {
+    return __builtin_fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+  }
   __device__ __forceinline__ V load_signed(int64_t x) const {
     // |x| < 2^53 here (plaintext integers); reduce into (-q, q)
     double d = (double)x;
     return __builtin_fma(-__builtin_rint(d * qinv), q, d);
   }
   __device__ __forceinline__ V reduce(V x) const { return __builtin_fma(-__builtin_rint(x * qinv), q, x); }
+  // canonical residue of x, split exactly into 32-bit halves (0 <= r < 2^50)
   __device__ __forceinline__ uint64_t store(V x) const {
     double r = reduce(x);          // |r| <= q/2 + 2
     r = r < 0.0 ? r + q : r;
-    return (uint64_t)r;
+    const uint32_t hi = (uint32_t)(r * 2.3283064365386963e-10);   // exact scaling by 2^-32, truncation
+    const uint32_t lo = (uint32_t)__builtin_fma(-(double)hi, 4294967296.0, r);
+    return ((uint64_t)hi << 32) | lo;
   }
   __device__ __forceinline__ V mul(V y, double w, double wq) const {
     double h = y * w;

@@ -24,6 +24,8 @@ struct he_batch {
   he::PJob *d_jobs = nullptr;
   uint32_t *d_ctl = nullptr;
   uint32_t n_tasks = 0, ctl_words = 0, grid = 0;
+  int slab = 14;
+  uint32_t strict = 0;
   std::vector<he::PJob> h_jobs;
   std::vector<size_t> ct_hat_off, pt_hat_off;
   hipStream_t cap = nullptr;
@@ -117,9 +119,17 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   release(b);
   hipError_t e = hipSetDevice(b->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  b->strict = (flags & HE_BATCH_STRICT_SYNC) ? 1u : 0u;
   bool all_f64 = true;
-  for (auto &j : b->jobs) all_f64 = all_f64 && j.ctx->f64_ok;
+  uint32_t max_logn = 10;
+  for (auto &j : b->jobs) {
+    all_f64 = all_f64 && j.ctx->f64_ok;
+    max_logn = std::max(max_logn, j.ctx->logN);
+  }
   b->arith = all_f64 ? HE_ARITH_F64 : HE_ARITH_U64;
+  // 8192-coefficient slabs (512 threads, two workgroups per CU) unless a job needs 16384
+  b->slab = max_logn >= 14 ? 14 : 13;
+  const uint32_t slab_n = 1u << b->slab;
   // workspace: transformed inputs and plaintexts per job
   const size_t nj = b->jobs.size();
   b->ct_hat_off.assign(nj, 0);
@@ -154,7 +164,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
     }
     const BJob &bj = b->jobs[j];
     const he_plan_info &in = bj.plan->info;
-    const uint32_t G = 16384u >> bj.ctx->logN, L = bj.ctx->L;
+    const uint32_t G = slab_n >> bj.ctx->logN, L = bj.ctx->L;
     const size_t before = tasks.size();
     if (!(bj.job.flags & HE_IN_NTT)) {
       const uint32_t planes = in.n_ct_in * 2 * L;
@@ -168,7 +178,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   }
   for (size_t j = 0; j < nj; ++j) {
     const BJob &bj = b->jobs[j];
-    const uint32_t G = 16384u >> bj.ctx->logN;
+    const uint32_t G = slab_n >> bj.ctx->logN;
     const uint32_t planes = bj.plan->info.n_ct_out * 2 * bj.ctx->L;
     for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
     info.inv_planes += planes;
@@ -182,7 +192,8 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
     release(b);
     return hip_fail(e, "device attribute");
   }
-  b->grid = (uint32_t)std::max(1, std::min<int>(cus, (int)std::max<uint32_t>(1u, b->n_tasks)));
+  const int per_cu = b->slab == 14 ? 1 : 2;
+  b->grid = (uint32_t)std::max(1, std::min<int>(cus * per_cu, (int)std::max<uint32_t>(1u, b->n_tasks)));
   if ((e = hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(PTask))) != hipSuccess ||
       (e = hipMalloc(&b->d_jobs, std::max<size_t>(1, nj) * sizeof(PJob))) != hipSuccess ||
       (e = hipMalloc(&b->d_ctl, b->ctl_words * 4)) != hipSuccess ||
@@ -203,8 +214,8 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
       release(b);
       return hip_fail(e, "graph capture");
     }
-    hipError_t le = launch_persistent(b->arith, b->d_tasks, b->n_tasks, b->d_jobs, b->d_ctl, b->ctl_words, b->grid,
-                                      b->spin_limit, b->cap);
+    hipError_t le = launch_persistent(b->arith, b->slab, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)nj, b->d_ctl,
+                                      b->ctl_words, b->grid, b->spin_limit, b->strict, b->cap);
     e = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess || e != hipSuccess ||
         (e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
@@ -242,8 +253,8 @@ he_status he_batch_run(he_batch *b, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (b->exec) e = hipGraphLaunch(b->exec, st);
-  else e = launch_persistent(b->arith, b->d_tasks, b->n_tasks, b->d_jobs, b->d_ctl, b->ctl_words, b->grid,
-                             b->spin_limit, st);
+  else e = launch_persistent(b->arith, b->slab, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)b->jobs.size(), b->d_ctl,
+                             b->ctl_words, b->grid, b->spin_limit, b->strict, st);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   return HE_OK;
 }

@@ -30,8 +30,9 @@ struct PJob {
   uint32_t pad_;
 };
 
-size_t persistent_lds_bytes();
-hipError_t launch_persistent(int arith, const PTask *tasks, uint32_t n_tasks, const PJob *jobs, uint32_t *ctl,
-                             uint32_t ctl_words, uint32_t grid, uint32_t spin_limit, hipStream_t st);
+size_t persistent_lds_bytes(int slab);
+hipError_t launch_persistent(int arith, int slab, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
+                             uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
+                             uint32_t strict, hipStream_t st);
 
 }  // namespace he

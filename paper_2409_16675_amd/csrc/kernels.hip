@@ -18,7 +18,7 @@ __device__ __forceinline__ uint64_t canon_add(const A &, uint64_t a, uint64_t b,
 
 // -------------------------------------------------------------- transforms
 template <class A, int LOGN, int LOGT>
-__global__ __launch_bounds__(1 << LOGT) void k_ntt_fwd(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
                                                        const PrimeK *__restrict__ primes,
                                                        const typename A::Tw *__restrict__ tw, int L) {
   using G = Geo<LOGN, LOGT>;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(1 << LOGT) void k_ntt_fwd(uint64_t *__restrict__ ou
 // Forward transform of signed integer polynomials lifted to every prime:
 // plane p reads polynomial p / L and lifts it modulo q_{p % L}.
 template <class A, int LOGN, int LOGT>
-__global__ __launch_bounds__(1 << LOGT) void k_ntt_fwd_lift(uint64_t *__restrict__ out,
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd_lift(uint64_t *__restrict__ out,
                                                             const int64_t *__restrict__ polys,
                                                             const PrimeK *__restrict__ primes,
                                                             const typename A::Tw *__restrict__ tw, int L) {
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(1 << LOGT) void k_ntt_fwd_lift(uint64_t *__restrict
 }
 
 template <class A, int LOGN, int LOGT>
-__global__ __launch_bounds__(1 << LOGT) void k_ntt_inv(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_inv(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
                                                        const PrimeK *__restrict__ primes,
                                                        const typename A::Tw *__restrict__ tw, int L) {
   using G = Geo<LOGN, LOGT>;
@@ -139,11 +139,10 @@ __device__ __forceinline__ int term_pt(const TermArgs &ta, int t) { return ta.ro
 
 // One workgroup per output plane (o, comp, i): multiply-accumulate the slots in
 // linear order into LDS, then the inverse transform, then store (or add).
-template <class A, int LOGN, int LOGT>
-__global__ __launch_bounds__(1 << LOGT) void k_mac_inv(uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat,
-                                                       const uint64_t *__restrict__ pt_hat, TermArgs ta,
-                                                       const PrimeK *__restrict__ primes,
-                                                       const typename A::Tw *__restrict__ tw, int L, int accumulate) {
+template <class A, int LOGN, int LOGT, bool ACC>
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_mac_inv(
+    uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat, const uint64_t *__restrict__ pt_hat, TermArgs ta,
+    const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, int L) {
   using G = Geo<LOGN, LOGT>;
   extern __shared__ __align__(16) unsigned char smem[];
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
@@ -177,7 +176,7 @@ __global__ __launch_bounds__(1 << LOGT) void k_mac_inv(uint64_t *__restrict__ ou
   for (int j = 0; j < G::E; ++j) lds[lpad(j * G::NT + tid)] = acc[j].value();
   uint64_t *dst = out + (size_t)plane * G::N;
   const uint64_t q = pk->q;
-  if (accumulate) {
+  if constexpr (ACC) {
     auto st = [&](int k, uint64_t v) { dst[k] = canon_add(ar, dst[k], v, q); };
     ntt_inverse_from_lds<A, G, 51>(ar, tw + (size_t)i * G::N, tid, lds, st);
   } else {
@@ -391,9 +390,15 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
                          tw_ptr<A>(c, true), (int)c.L);
       break;
     case OP_MAC_INV:
-      if ((e = prep(k_mac_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.pt, la.ta,
-                         c.d_primes, tw_ptr<A>(c, true), (int)c.L, la.accumulate);
+      if (la.accumulate) {
+        if ((e = prep(k_mac_inv<A, LOGN, LOGT, true>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, true>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
+                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L);
+      } else {
+        if ((e = prep(k_mac_inv<A, LOGN, LOGT, false>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
+                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L);
+      }
       break;
   }
   return hipGetLastError();

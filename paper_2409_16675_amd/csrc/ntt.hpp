@@ -33,6 +33,17 @@ struct Geo {
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 
+// Waves per SIMD two (or more) resident workgroups need, given the LDS a plane
+// takes: passed as the second __launch_bounds__ argument so that the compiler
+// keeps the register count low enough for that occupancy.
+template <int LOGN, int LOGT>
+struct MinWaves {
+  static constexpr int lds = ((1 << LOGN) + (1 << (LOGN - 5))) * 8 + 256;
+  static constexpr int wg = (163840 / lds) < 1 ? 1 : (163840 / lds);
+  static constexpr int w = wg * (1 << LOGT) / 64 / 4;
+  static constexpr int value = w < 1 ? 1 : (w > 8 ? 8 : w);
+};
+
 // Index of register slot (g, p) of thread tid in a pass starting at stage S0 with R stages.
 template <int LOGN, int LOGT, int S0, int R>
 __device__ __forceinline__ int pass_index(int tid, int g, int p) {
@@ -88,6 +99,52 @@ constexpr PassPlan plan_gs(int R, double b_in) {
   return p;
 }
 
+// Inverse passes track the bound of every register slot p of a radix-2^R group:
+// the Gentleman-Sande sum x + y doubles the bound of the slots whose lower pass
+// bits are zero while the product side stays below mul_out, so only the
+// growing slots are reduced (before a stage whose sum would leave the limit,
+// and at the end of the pass when above kEndRed).
+struct GsPlan {
+  uint32_t red[6];   // red[uu]: slots reduced before stage uu; red[R]: slots reduced at the end
+  double b_out;
+};
+constexpr double kEndRed = 2.0;
+
+template <class A>
+constexpr GsPlan plan_gs_slots(int R, double b_in) {
+  GsPlan pl{{0u, 0u, 0u, 0u, 0u, 0u}, b_in};
+  double b[32] = {};
+  const int n = 1 << R;
+  for (int p = 0; p < n; ++p) b[p] = b_in;
+  for (int uu = 0; uu < R; ++uu) {
+    uint32_t m = 0;
+    for (int p = 0; p < n; ++p) {
+      if (p & (1 << uu)) continue;
+      const int p2 = p | (1 << uu);
+      double s = b[p] + b[p2];
+      if (s > A::kLimit || A::mul_out(s) > A::kLimit) {
+        m |= (1u << p) | (1u << p2);
+        s = 2.0 * A::kReduced;
+      }
+      b[p] = s;
+      b[p2] = A::mul_out(s);
+    }
+    pl.red[uu] = m;
+  }
+  uint32_t e = 0;
+  double mx = 0.0;
+  for (int p = 0; p < n; ++p) {
+    if (b[p] > kEndRed && A::kLimit < 100.0) {
+      e |= 1u << p;
+      b[p] = A::kReduced;
+    }
+    mx = b[p] > mx ? b[p] : mx;
+  }
+  pl.red[R] = e;
+  pl.b_out = mx;
+  return pl;
+}
+
 // Bound entering forward pass k (passes run 0, 1, ..., each starting from the previous output).
 template <class A, class G>
 constexpr double fwd_bound_in(int k) {
@@ -99,7 +156,7 @@ constexpr double fwd_bound_in(int k) {
 template <class A, class G>
 constexpr double inv_bound_in(int k, double b0) {
   double b = b0;
-  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs<A>(G::r(j), b).b_out;
+  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs_slots<A>(G::r(j), b).b_out;
   return b;
 }
 
@@ -189,7 +246,8 @@ template <class A, class G, int K, int B0X100, class Ld, class St>
 __device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__restrict__ tw, int tid, Ld ld, St st) {
   using V = typename A::V;
   constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
-  constexpr PassPlan pp = plan_gs<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
+  constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
+  static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
   V v[G::E];
 #pragma unroll
   for (int g = 0; g < NG; ++g)
@@ -198,10 +256,9 @@ __device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__re
 #pragma unroll
   for (int uu = 0; uu < R; ++uu) {
     const int u = R - 1 - uu;   // stage S0 + u, processed from the highest down
-    if ((pp.mask >> uu) & 1u) {
 #pragma unroll
-      for (int e = 0; e < G::E; ++e) v[e] = ar.reduce(v[e]);
-    }
+    for (int e = 0; e < G::E; ++e)
+      if ((pp.red[uu] >> (e & ((1 << R) - 1))) & 1u) v[e] = ar.reduce(v[e]);
     const int s = S0 + u;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -219,6 +276,9 @@ __device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__re
       }
     }
   }
+#pragma unroll
+  for (int e = 0; e < G::E; ++e)
+    if ((pp.red[R] >> (e & ((1 << R) - 1))) & 1u) v[e] = ar.reduce(v[e]);
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll

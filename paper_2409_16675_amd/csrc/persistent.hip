@@ -20,6 +20,9 @@
 
 namespace he {
 
+// s_waitcnt immediate for gfx9-family: vmcnt = 0, expcnt and lgkmcnt left at their maxima
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 template <class A>
 struct PTw;
 template <>
@@ -169,24 +172,49 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   }
 }
 
-template <class A>
-__global__ __launch_bounds__(1024) void k_persistent(const PTask *__restrict__ tasks, uint32_t n_tasks,
-                                                     const PJob *__restrict__ jobs, uint32_t *__restrict__ ctl,
-                                                     uint32_t spin_limit) {
+// SLAB = log2 of the coefficients one workgroup holds (14: 1024 threads, one
+// workgroup per CU, ring degrees up to 16384; 13: 512 threads, two per CU,
+// ring degrees up to 8192).  A job's readiness is acquired once per workgroup:
+// after the first acquire (which invalidates this CU's caches after the
+// producers' release) later tasks of the same job read the finished data.
+template <class A, int SLAB>
+__global__ __launch_bounds__(1 << (SLAB - 4), (SLAB == 14 ? 4 : 4)) void k_persistent(
+    const PTask *__restrict__ tasks, uint32_t n_tasks, const PJob *__restrict__ jobs, uint32_t n_jobs,
+    uint32_t *__restrict__ ctl, uint32_t spin_limit, uint32_t strict) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_task;
+  __shared__ uint32_t s_task, s_wait;
+  __shared__ uint32_t s_ready[64];   // acquired jobs (bitmap, jobs < 2048); touched by thread 0 only
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
   const int tid = threadIdx.x;
   uint32_t *head = ctl + CTL_HEAD, *err = ctl + CTL_ERR, *done = ctl + CTL_DONE;
+  if (tid == 0)
+    for (int k = 0; k < 64; ++k) s_ready[k] = 0u;
+  // The launch may be a graph replay whose dispatch does not invalidate this XCD's
+  // L2: drop any line cached before the launch (inputs written by copies or by
+  // kernels on other XCDs) before reading anything.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
   for (;;) {
-    if (tid == 0) s_task = atomicAdd(head, 1u);
+    // thread 0 takes the next task and decides, for the whole workgroup, whether
+    // it must wait for the job's pre tasks (so every thread takes the same branch)
+    if (tid == 0) {
+      const uint32_t t0 = atomicAdd(head, 1u);
+      uint32_t w = 0;
+      if (t0 < n_tasks) {
+        const PTask k0 = tasks[t0];
+        if (k0.kind == PT_MAC_INV && jobs[k0.job].n_pre)
+          w = (!strict && k0.job < 2048 && ((s_ready[k0.job >> 5] >> (k0.job & 31)) & 1u)) ? 0u : 1u;
+      }
+      s_task = t0;
+      s_wait = w;
+    }
     __syncthreads();
     const uint32_t t = s_task;
+    const uint32_t must_wait = s_wait;
     __syncthreads();
     if (t >= n_tasks) break;
     const PTask tk = tasks[t];
     const PJob &jb = jobs[tk.job];
-    if (tk.kind == PT_MAC_INV && jb.n_pre) {
+    if (must_wait) {
       if (tid == 0) {
         uint32_t spins = 0;
         while (__hip_atomic_load(done + tk.job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jb.n_pre) {
@@ -197,9 +225,10 @@ __global__ __launch_bounds__(1024) void k_persistent(const PTask *__restrict__ t
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (tk.job < 2048) s_ready[tk.job >> 5] |= 1u << (tk.job & 31);
       }
       __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (strict) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     const int logn = (int)jb.logN;
     const int logt = logn - 4;
@@ -212,12 +241,22 @@ __global__ __launch_bounds__(1024) void k_persistent(const PTask *__restrict__ t
       case 11: run_task<A, 11>(tk, jb, tid_g, group, lds_g); break;
       case 12: run_task<A, 12>(tk, jb, tid_g, group, lds_g); break;
       case 13: run_task<A, 13>(tk, jb, tid_g, group, lds_g); break;
-      default: run_task<A, 14>(tk, jb, tid_g, group, lds_g); break;
+      default:
+        if constexpr (SLAB >= 14) run_task<A, 14>(tk, jb, tid_g, group, lds_g);
+        break;
+    }
+    if (tk.kind != PT_MAC_INV) {
+      // every wave waits until its own global stores have reached L2 (the barrier
+      // alone orders LDS only); thread 0's release then writes L2 back and publishes
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      if (strict) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();
     if (tk.kind != PT_MAC_INV && tid == 0)
       __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // write this workgroup's outputs back from L2 before the launch ends (same reason)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 }
 
 // Zero the queue head, the error flag and the per-job counters (a kernel, not a
@@ -226,32 +265,35 @@ __global__ void k_reset_ctl(uint32_t *ctl, uint32_t n_words) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_words; k += gridDim.x * blockDim.x) ctl[k] = 0u;
 }
 
-size_t persistent_lds_bytes() { return (size_t)(16384 + 512) * 8; }
+size_t persistent_lds_bytes(int slab) { return (size_t)((1 << slab) + (1 << (slab - 5))) * 8; }
 
-hipError_t launch_persistent(int arith, const PTask *tasks, uint32_t n_tasks, const PJob *jobs, uint32_t *ctl,
-                             uint32_t ctl_words, uint32_t grid, uint32_t spin_limit, hipStream_t st) {
-  const size_t lds = persistent_lds_bytes();
+template <class A, int SLAB>
+static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const PJob *jobs, uint32_t n_jobs, uint32_t *ctl,
+                           uint32_t grid, uint32_t spin_limit, uint32_t strict, hipStream_t st) {
+  const size_t lds = persistent_lds_bytes(SLAB);
+  static bool set = false;
+  if (!set) {
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_persistent<A, SLAB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    set = true;
+  }
+  hipLaunchKernelGGL((k_persistent<A, SLAB>), dim3(grid), dim3(1 << (SLAB - 4)), lds, st, tasks, n_tasks, jobs, n_jobs,
+                     ctl, spin_limit, strict);
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent(int arith, int slab, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
+                             uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
+                             uint32_t strict, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ctl, ctl_words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (arith == HE_ARITH_F64) {
-    static bool set = false;
-    if (!set) {
-      e = hipFuncSetAttribute((const void *)k_persistent<ArF64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      set = true;
-    }
-    hipLaunchKernelGGL(k_persistent<ArF64>, dim3(grid), dim3(1024), lds, st, tasks, n_tasks, jobs, ctl, spin_limit);
-  } else {
-    static bool set = false;
-    if (!set) {
-      e = hipFuncSetAttribute((const void *)k_persistent<ArU64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      set = true;
-    }
-    hipLaunchKernelGGL(k_persistent<ArU64>, dim3(grid), dim3(1024), lds, st, tasks, n_tasks, jobs, ctl, spin_limit);
-  }
-  return hipGetLastError();
+  if (arith == HE_ARITH_F64)
+    return slab == 14 ? launch_p<ArF64, 14>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
+                      : launch_p<ArF64, 13>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st);
+  return slab == 14 ? launch_p<ArU64, 14>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
+                    : launch_p<ArU64, 13>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st);
 }
 
 }  // namespace he

@@ -1,0 +1,171 @@
+// Autotuner for the transform and fused multiply-accumulate schedules.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <random>
+#include <sstream>
+#include <string>
+
+#include "plan.hpp"
+
+using namespace he;
+
+namespace {
+
+std::string arch_name(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string cache_key(const Ctx &c) {
+  std::ostringstream k;
+  k << "\"arch\": \"" << arch_name(c.device) << "\", \"N\": " << c.N << ", \"L\": " << c.L << ", \"q0\": " << c.q[0];
+  return k.str();
+}
+
+bool read_cache(const char *path, const std::string &key, Sched out[3]) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    if (line.find(key) == std::string::npos) continue;
+    int v[6];
+    const size_t s = line.find("\"sched\": [");
+    if (s == std::string::npos) continue;
+    if (std::sscanf(line.c_str() + s, "\"sched\": [%d, %d, %d, %d, %d, %d]", &v[0], &v[1], &v[2], &v[3], &v[4],
+                    &v[5]) == 6) {
+      for (int k = 0; k < 3; ++k) out[k] = Sched{v[2 * k], v[2 * k + 1]};
+      found = true;   // the last matching line wins
+    }
+  }
+  return found;
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer() {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+extern "C" he_status he_autotune(he_ctx *ctx, uint32_t n_polys, const char *cache_path, void *stream,
+                                 he_tune_entry *report, uint32_t report_cap, uint32_t *report_n) {
+  if (!ctx) return fail(HE_EINVAL, "null context");
+  Ctx &c = *ctx->c;
+  hipStream_t st = (hipStream_t)stream;
+  if (report_n) *report_n = 0;
+  const std::string key = cache_key(c);
+  if (cache_path) {
+    Sched s[3];
+    if (read_cache(cache_path, key, s)) {
+      bool ok = true;
+      for (auto &x : s) ok = ok && sched_valid(c.logN, x) && (x.arith != HE_ARITH_F64 || c.f64_ok);
+      if (ok) {
+        c.s_fwd = s[0];
+        c.s_inv = s[1];
+        c.s_mac = s[2];
+        return HE_OK;
+      }
+    }
+  }
+  if (n_polys == 0) n_polys = 512;
+  if (n_polys % 2) ++n_polys;
+  const size_t planes = (size_t)n_polys * c.L, words = planes * c.N;
+  // seeded canonical data
+  std::vector<uint64_t> h(words);
+  std::mt19937_64 g(0x5eedu + c.N + c.L);
+  for (size_t k = 0; k < words; ++k) h[k] = g() % c.q[(k / c.N) % c.L];
+  uint64_t *d = nullptr;
+  hipError_t e = hipMalloc(&d, words * 8 * 5);
+  if (e != hipSuccess) return hip_fail(e, "autotune scratch");
+  uint64_t *in = d, *ref = d + words, *out = d + 2 * words, *pt = d + 3 * words, *refm = d + 4 * words;
+  std::vector<uint64_t> hout(words), href(words);
+  int32_t *d_terms_keep = nullptr;
+  auto fail_free = [&](hipError_t err, const char *what) {
+    (void)hipFree(d);
+    if (d_terms_keep) (void)hipFree(d_terms_keep);
+    return hip_fail(err, what);
+  };
+  if ((e = hipMemcpy(in, h.data(), words * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail_free(e, "upload");
+  for (size_t k = 0; k < words; ++k) h[k] = g() % c.q[(k / c.N) % c.L];
+  if ((e = hipMemcpy(pt, h.data(), words * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail_free(e, "upload");
+  // term lists for the fused kernel: output o = ct[o] (x) pt[o], one term each
+  const uint32_t n_out = (uint32_t)(n_polys / 2);
+  std::vector<int32_t> tl(3 * (size_t)n_out + 1);
+  for (uint32_t o = 0; o <= n_out; ++o) tl[o] = (int32_t)o;
+  for (uint32_t o = 0; o < n_out; ++o) tl[n_out + 1 + o] = tl[2 * n_out + 1 + o] = (int32_t)o;
+  int32_t *d_terms = nullptr;
+  if ((e = hipMalloc(&d_terms, tl.size() * 4)) != hipSuccess) return fail_free(e, "terms");
+  d_terms_keep = d_terms;
+  if ((e = hipMemcpy(d_terms, tl.data(), tl.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) return fail_free(e, "terms");
+  const std::vector<Sched> cands = schedules_for(c.logN, c.f64_ok);
+  Timer tm;
+  const int reps = 5;
+  Sched best[3];
+  uint32_t nrep = 0;
+  for (int op = 0; op < 3; ++op) {
+    double best_us = 1e30;
+    best[op] = cands[0];
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      const Sched &s = cands[ci];
+      Terms terms;
+      terms.row = d_terms;
+      terms.cti = d_terms + n_out + 1;
+      terms.pti = d_terms + 2 * n_out + 1;
+      terms.n_out = n_out;
+      auto launch = [&]() -> hipError_t {
+        if (op == HE_OP_FWD) return launch_ntt_fwd(c, s, out, in, (uint32_t)planes, st);
+        if (op == HE_OP_INV) return launch_ntt_inv(c, s, out, in, (uint32_t)planes, st);
+        return launch_mac(c, s, out, in, pt, terms, false, false, st);
+      };
+      if ((e = launch()) != hipSuccess) return fail_free(e, "autotune launch");
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_free(e, "autotune sync");
+      if ((e = hipEventRecord(tm.a, st)) != hipSuccess) return fail_free(e, "event");
+      for (int r = 0; r < reps; ++r)
+        if ((e = launch()) != hipSuccess) return fail_free(e, "autotune launch");
+      if ((e = hipEventRecord(tm.b, st)) != hipSuccess || (e = hipEventSynchronize(tm.b)) != hipSuccess)
+        return fail_free(e, "event");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, tm.a, tm.b);
+      const double us = 1e3 * ms / reps;
+      const size_t cmp_words = words;
+      if ((e = hipMemcpy(hout.data(), out, cmp_words * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail_free(e, "download");
+      bool exact = true;
+      if (ci == 0) href.assign(hout.begin(), hout.begin() + cmp_words);
+      else exact = std::memcmp(href.data(), hout.data(), cmp_words * 8) == 0;
+      if (report && nrep < report_cap) report[nrep] = he_tune_entry{(uint32_t)op, (uint32_t)s.arith, (uint32_t)s.loge,
+                                                                     exact ? 1u : 0u, us};
+      ++nrep;
+      if (exact && us < best_us) {
+        best_us = us;
+        best[op] = s;
+      }
+    }
+  }
+  (void)hipFree(d);
+  (void)hipFree(d_terms);
+  (void)refm;
+  c.s_fwd = best[0];
+  c.s_inv = best[1];
+  c.s_mac = best[2];
+  if (report_n) *report_n = nrep < report_cap ? nrep : report_cap;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    if (f)
+      f << "{" << key << ", \"sched\": [" << best[0].arith << ", " << best[0].loge << ", " << best[1].arith << ", "
+        << best[1].loge << ", " << best[2].arith << ", " << best[2].loge << "]}\n";
+  }
+  return HE_OK;
+}

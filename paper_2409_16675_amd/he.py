@@ -71,6 +71,7 @@ _SIGS = {
     "he_extract_output": [c_void_p, i64p, i64p],
     "he_encrypt": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "he_decrypt": [c_void_p, c_void_p, c_void_p, c_u32, i64p, c_void_p],
+    "he_autotune": [c_void_p, c_u32, ctypes.c_char_p, c_void_p, c_void_p, c_u32, ctypes.POINTER(c_u32)],
     "he_batch_create": [c_i32, ctypes.POINTER(c_void_p)],
     "he_batch_add": [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_u32)],
     "he_batch_build": [c_void_p, c_u32],
@@ -282,6 +283,20 @@ def he_decrypt(ctx, s, ct, n_ct, N, stream=None):
     m = np.zeros(n_ct * N, dtype=np.int64)
     _chk(_lib.he_decrypt(ctx, _ptr(s), _ptr(ct), n_ct, m.ctypes.data_as(i64p), _stream(stream)), "he_decrypt")
     return m.reshape(n_ct, N)
+
+
+# ------------------------------------------------------------------ autotuning
+class he_tune_entry(ctypes.Structure):
+    _fields_ = [("op", c_u32), ("arith", c_u32), ("loge", c_u32), ("exact", c_u32), ("us", ctypes.c_double)]
+
+
+def he_autotune(ctx, n_polys=512, cache_path=None, stream=None):
+    arr = (he_tune_entry * 64)()
+    n = c_u32()
+    _chk(_lib.he_autotune(ctx, n_polys, cache_path.encode() if cache_path else None, _stream(stream),
+                          ctypes.cast(arr, c_void_p), 64, ctypes.byref(n)), "he_autotune")
+    return [dict(op=arr[i].op, arith=arr[i].arith, loge=arr[i].loge, exact=bool(arr[i].exact), us=arr[i].us)
+            for i in range(n.value)]
 
 
 # ------------------------------------------------------------------ batching

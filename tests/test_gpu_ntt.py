@@ -105,3 +105,30 @@ def test_ntt_large_batch_sampled_against_definition(gpu_lib):
     he.he_ntt_inv(ctx.h, d, n_polys)
     torch.cuda.synchronize()
     assert_equal_u64(he.to_numpy_u64(d), x, "roundtrip")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 50), (4096, 2, 60)])
+def test_autotune_candidates_are_all_exact_and_chosen_one_is_installed(gpu_lib, N, L, bits, tmp_path):
+    he = gpu_lib
+    ctx = he.Context(N, L, prime_bits=bits)
+    cache = str(tmp_path / "tune.jsonl")
+    rep = he.he_autotune(ctx.h, 64, cache)
+    assert rep and all(r["exact"] for r in rep)
+    n_sched = len(he.compiled_schedules(N, f64_ok=bits <= 50))
+    assert len(rep) == 3 * n_sched
+    chosen = [he.he_ctx_get_schedule(ctx.h, op) for op in (he.HE_OP_FWD, he.HE_OP_INV, he.HE_OP_MAC)]
+    for op, (a, le) in enumerate(chosen):
+        best = min((r for r in rep if r["op"] == op), key=lambda r: r["us"])
+        assert (a, le) == (best["arith"], best["loge"])
+    # a second context reads the cache instead of timing, and gets the same schedules
+    ctx2 = he.Context(N, L, prime_bits=bits)
+    assert he.he_autotune(ctx2.h, 64, cache) == []
+    assert [he.he_ctx_get_schedule(ctx2.h, op) for op in (he.HE_OP_FWD, he.HE_OP_INV, he.HE_OP_MAC)] == chosen
+    # transforms with the tuned schedules still match the oracle
+    g = synth.rng(94, N)
+    x = synth.uniform_residues(g, (2,), ctx2.q, N)
+    d = he.to_device_u64(x)
+    he.he_ntt_fwd(ctx2.h, d, 2)
+    torch.cuda.synchronize()
+    assert_equal_u64(he.to_numpy_u64(d), core.ntt_planes(x, ctx2.q, ctx2.psi), "tuned fwd")
