@@ -270,6 +270,66 @@ he_status he_batch_sync(he_batch *b, void *stream);
 he_status he_batch_get_info(const he_batch *b, he_batch_info *info);
 he_status he_batch_destroy(he_batch *b);
 
+/* ------------------------------------------------------------------- serving */
+/* A request loop for homomorphic linear-layer jobs.  Jobs (he_job: plan and
+ * device buffers owned by the caller) are queued FIFO and admitted while the
+ * device footprint of admitted, unfinished work stays within mem_cap_bytes;
+ * footprint = the job's workspace + its input and output ciphertexts + the
+ * transformed inputs that jobs of open sessions keep resident.  In CONTINUOUS
+ * mode every admitted job not yet running is launched as one persistent-kernel
+ * epoch on a free stream slot, so jobs that arrive while an epoch runs go into
+ * the next epoch on another stream and overlap on the device; SEQUENTIAL mode
+ * serves one job at a time through the per-layer path (the plain baseline).
+ * Latency is measured from arrival (submission, or the scheduled arrival in
+ * he_server_replay) to completion observed by the server thread. */
+#define HE_SERVE_CONTINUOUS 0
+#define HE_SERVE_SEQUENTIAL 1
+#define HE_SERVE_KEEP_RESIDENT 0x1u   /* he_server_submit flag: keep the job's transformed inputs until its session closes */
+
+typedef struct {
+  int32_t device;
+  uint32_t mode;              /* HE_SERVE_* */
+  uint64_t mem_cap_bytes;     /* admission cap on the device footprint */
+  uint64_t arena_bytes;       /* device arena for workspaces (0: min(cap, 8 GiB)); allocated at creation */
+  uint32_t max_batch_jobs;    /* jobs per epoch (0: 64) */
+  uint32_t slots;             /* concurrent epochs on separate streams (0: 2, at most 8) */
+  uint32_t session_jobs;      /* a session closes after this many jobs (0: never, resident data is kept) */
+  uint32_t poll_us;           /* completion polling period of the server thread (0: 20) */
+} he_server_params;
+
+typedef struct {
+  he_status status;
+  double latency_s;           /* arrival to completion */
+  double queue_s;             /* arrival to launch */
+} he_job_result;
+
+typedef struct {
+  uint64_t completed, rejected, epochs;
+  double mean_jobs_per_epoch;
+  double p50_s, p99_s, mean_s, max_s;
+  double span_s;              /* first arrival to last completion */
+  uint64_t peak_bytes, in_use_bytes;
+} he_server_info;
+
+/* Start a server (device arena, stream slots and the server thread). */
+he_status he_server_create(const he_server_params *params, he_server **out);
+/* Queue a job; HE_EBUSY if its footprint alone exceeds the cap.  `session` (0 =
+ * none) groups the jobs of one training step; with HE_SERVE_KEEP_RESIDENT the
+ * job's transformed inputs stay on the device until the session closes. */
+he_status he_server_submit(he_server *s, he_ctx *ctx, const he_job *job, uint64_t session, uint32_t flags,
+                           uint64_t *ticket);
+/* Wait for a job (timeout_us < 0: no limit); returns the job's status or HE_ETIMEOUT. */
+he_status he_server_wait(he_server *s, uint64_t ticket, int64_t timeout_us, he_job_result *result);
+/* Wait until every queued job has finished. */
+he_status he_server_drain(he_server *s);
+/* Submit n jobs at arrival_s[i] seconds after the call (busy-waiting on the host
+ * clock), wait for all, and write each latency (from its scheduled arrival) to
+ * latency_s[i] (host, may be NULL; -1 for a rejected job). */
+he_status he_server_replay(he_server *s, uint32_t n, he_ctx *const *ctxs, const he_job *jobs, const double *arrival_s,
+                           const uint64_t *sessions, uint32_t flags, double *latency_s);
+he_status he_server_stats(he_server *s, he_server_info *out);
+he_status he_server_destroy(he_server *s);
+
 /* ------------------------------------------------------------ kernel timing */
 /* Per-kernel timing on the launch stream: while enabled, every kernel the
  * context's calls launch is bracketed by two HIP events on the stream it is

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhe.so")
 
-SOURCES = ["kernels.hip", "persistent.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp"]
+SOURCES = ["kernels.hip", "persistent.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-ffp-contract=off",
@@ -22,8 +22,20 @@ FLAGS = [
 ]
 
 
-def _compile(src):
+def _deps_newer(src, out):
+    """True when the object is missing or older than the source or any header."""
+    if not os.path.exists(out):
+        return True
+    t = os.path.getmtime(out)
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hdrs.append(os.path.join(ROOT, "include", "he.h"))
+    return any(os.path.getmtime(f) > t for f in [os.path.join(CSRC, src)] + hdrs)
+
+
+def _compile(src, incremental=False):
     out = os.path.join(BUILD, src + ".o")
+    if incremental and not _deps_newer(src, out):
+        return out
     cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
@@ -33,10 +45,11 @@ def _compile(src):
     return out
 
 
-def build(verbose=False):
+def build(verbose=False, incremental=False):
+    """Compile every source (incremental=True skips objects newer than their inputs)."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,5 +62,5 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

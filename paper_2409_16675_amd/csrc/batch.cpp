@@ -5,17 +5,10 @@
 #include "batch.hpp"
 #include "plan.hpp"
 
-namespace he {
-struct BJob {
-  Ctx *ctx;
-  const Plan *plan;
-  he_job job;
-};
-}  // namespace he
 
 struct he_batch {
   int device = 0;
-  std::vector<he::BJob> jobs;
+  std::vector<he::JobRef> jobs;
   bool built = false;
   int arith = HE_ARITH_F64;
   void *d_ws = nullptr;
@@ -24,10 +17,10 @@ struct he_batch {
   he::PJob *d_jobs = nullptr;
   uint32_t *d_ctl = nullptr;
   uint32_t n_tasks = 0, ctl_words = 0, grid = 0;
-  int slab = 14;
+  he::PVariant var{};
   uint32_t strict = 0;
   std::vector<he::PJob> h_jobs;
-  std::vector<size_t> ct_hat_off, pt_hat_off;
+  std::vector<char *> ws_ptrs;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -37,7 +30,6 @@ struct he_batch {
 
 using namespace he;
 
-static inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static void release(he_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -55,20 +47,33 @@ static void release(he_batch *b) {
   b->built = false;
 }
 
-static he_status fill_job(const he_batch *b, uint32_t idx, PJob &pj) {
-  const BJob &bj = b->jobs[idx];
+namespace he {
+
+static inline size_t al256b(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t job_ws_bytes(const JobRef &j) {
+  const he_plan_info &in = j.plan->info;
+  const size_t plane = (size_t)j.ctx->L * j.ctx->N * 8;
+  size_t b = al256b((size_t)in.n_pt * plane);
+  if (!(j.job.flags & HE_IN_NTT)) b += al256b((size_t)in.n_ct_in * 2 * plane);
+  return b;
+}
+
+static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
   const Ctx &c = *bj.ctx;
   const Plan &p = *bj.plan;
   const he_plan_info &in = p.info;
   const uint32_t f = bj.job.flags;
+  const size_t plane = (size_t)c.L * c.N * 8;
   pj = PJob{};
   pj.primes = c.d_primes;
-  pj.tw_fwd = b->arith == HE_ARITH_F64 ? c.d_tw_f64_fwd : c.d_tw_u64_fwd;
-  pj.tw_inv = b->arith == HE_ARITH_F64 ? c.d_tw_f64_inv : c.d_tw_u64_inv;
+  pj.tw_fwd = arith == HE_ARITH_F64 ? c.d_tw_f64_fwd : c.d_tw_u64_fwd;
+  pj.tw_inv = arith == HE_ARITH_F64 ? c.d_tw_f64_inv : c.d_tw_u64_inv;
   pj.ct_in = bj.job.ct_in;
-  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in) : (uint64_t *)((char *)b->d_ws + b->ct_hat_off[idx]);
+  pj.pt_hat = (uint64_t *)ws;
+  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in)
+                              : (uint64_t *)(ws + al256b((size_t)in.n_pt * plane));
   pj.plain = bj.job.plain;
-  pj.pt_hat = (uint64_t *)((char *)b->d_ws + b->pt_hat_off[idx]);
   pj.ct_out = bj.job.ct_out;
   pj.row = p.d_row();
   pj.cti = p.d_cti();
@@ -93,6 +98,47 @@ static he_status fill_job(const he_batch *b, uint32_t idx, PJob &pj) {
   return HE_OK;
 }
 
+he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *> &ws, int arith, int slab,
+                       std::vector<PTask> &tasks, std::vector<PJob> &pjobs, he_batch_info &info) {
+  const size_t nj = jobs.size();
+  const uint32_t slab_n = 1u << slab;
+  tasks.clear();
+  pjobs.assign(nj, PJob{});
+  info = he_batch_info{};
+  for (size_t j = 0; j < nj; ++j) {
+    he_status s = fill_job(jobs[j], ws[j], arith, pjobs[j]);
+    if (s != HE_OK) return s;
+    const JobRef &bj = jobs[j];
+    const he_plan_info &in = bj.plan->info;
+    if ((uint32_t)bj.ctx->logN > (uint32_t)slab) return fail(HE_EUNSUPPORTED, "ring degree above the kernel slab");
+    const uint32_t G = slab_n >> bj.ctx->logN, L = bj.ctx->L;
+    const size_t before = tasks.size();
+    if (!(bj.job.flags & HE_IN_NTT)) {
+      const uint32_t planes = in.n_ct_in * 2 * L;
+      for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p)});
+      info.fwd_planes += planes;
+    }
+    const uint32_t pplanes = in.n_pt * L;
+    for (uint32_t p = 0; p < pplanes; p += G) tasks.push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p)});
+    info.fwd_planes += pplanes;
+    pjobs[j].n_pre = (uint32_t)(tasks.size() - before);
+    info.cpmul += in.n_terms;
+  }
+  for (size_t j = 0; j < nj; ++j) {
+    const JobRef &bj = jobs[j];
+    const uint32_t G = slab_n >> bj.ctx->logN;
+    const uint32_t planes = bj.plan->info.n_ct_out * 2 * bj.ctx->L;
+    for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
+    info.inv_planes += planes;
+  }
+  info.n_jobs = (uint32_t)nj;
+  info.n_tasks = (uint32_t)tasks.size();
+  info.arith = (uint32_t)arith;
+  return HE_OK;
+}
+
+}  // namespace he
+
 extern "C" {
 
 he_status he_batch_create(int32_t device, he_batch **out) {
@@ -109,7 +155,7 @@ he_status he_batch_add(he_batch *b, he_ctx *ctx, const he_job *job, uint32_t *in
   if (!job->ct_in || !job->plain || !job->ct_out) return fail(HE_EINVAL, "null job buffer");
   if (ctx->c->device != b->device) return fail(HE_EINVAL, "context on another device");
   if (ctx->c->logN < 10 || ctx->c->logN > 14) return fail(HE_EUNSUPPORTED, "ring degree");
-  b->jobs.push_back(BJob{ctx->c, &job->plan->p, *job});
+  b->jobs.push_back(JobRef{ctx->c, &job->plan->p, *job});
   if (index) *index = (uint32_t)(b->jobs.size() - 1);
   return HE_OK;
 }
@@ -119,69 +165,41 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   release(b);
   hipError_t e = hipSetDevice(b->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  b->strict = (flags & HE_BATCH_STRICT_SYNC) ? 1u : 0u;
+  b->strict = ((flags & HE_BATCH_STRICT_SYNC) ? 1u : 0u) | ((flags >> 8) & 0xCu);   // bits 10, 11: timing probes
   bool all_f64 = true;
-  uint32_t max_logn = 10;
+  uint32_t max_logn = 10, min_logn = 14;
   for (auto &j : b->jobs) {
     all_f64 = all_f64 && j.ctx->f64_ok;
     max_logn = std::max(max_logn, j.ctx->logN);
+    min_logn = std::min(min_logn, j.ctx->logN);
   }
+  if (b->jobs.empty()) min_logn = max_logn;
   b->arith = all_f64 ? HE_ARITH_F64 : HE_ARITH_U64;
-  // 8192-coefficient slabs (512 threads, two workgroups per CU) unless a job needs 16384
-  b->slab = max_logn >= 14 ? 14 : 13;
-  const uint32_t slab_n = 1u << b->slab;
+  persistent_variant(b->arith, min_logn, max_logn, b->var);
+  const uint32_t slab_n = 1u << b->var.slab;
   // workspace: transformed inputs and plaintexts per job
   const size_t nj = b->jobs.size();
-  b->ct_hat_off.assign(nj, 0);
-  b->pt_hat_off.assign(nj, 0);
+  std::vector<size_t> offs(nj, 0);
   size_t off = 0;
-  he_batch_info info{};
   for (size_t j = 0; j < nj; ++j) {
-    const BJob &bj = b->jobs[j];
-    const he_plan_info &in = bj.plan->info;
-    const size_t plane = (size_t)bj.ctx->L * bj.ctx->N * 8;
-    if (!(bj.job.flags & HE_IN_NTT)) {
-      b->ct_hat_off[j] = off;
-      off += al256((size_t)in.n_ct_in * 2 * plane);
-    }
-    b->pt_hat_off[j] = off;
-    off += al256((size_t)in.n_pt * plane);
-    info.cpmul += in.n_terms;
+    offs[j] = off;
+    off += job_ws_bytes(b->jobs[j]);
   }
   b->ws_bytes = off;
   if (off && (e = hipMalloc(&b->d_ws, off)) != hipSuccess) {
     release(b);
     return hip_fail(e, "batch workspace");
   }
-  // task table: every job's pre tasks, then every job's multiply-accumulate tasks
+  std::vector<char *> wsp(nj);
+  for (size_t j = 0; j < nj; ++j) wsp[j] = (char *)b->d_ws + offs[j];
+  b->ws_ptrs = wsp;
   std::vector<PTask> tasks;
-  std::vector<PJob> pjobs(nj);
-  for (size_t j = 0; j < nj; ++j) {
-    he_status s = fill_job(b, (uint32_t)j, pjobs[j]);
-    if (s != HE_OK) {
-      release(b);
-      return s;
-    }
-    const BJob &bj = b->jobs[j];
-    const he_plan_info &in = bj.plan->info;
-    const uint32_t G = slab_n >> bj.ctx->logN, L = bj.ctx->L;
-    const size_t before = tasks.size();
-    if (!(bj.job.flags & HE_IN_NTT)) {
-      const uint32_t planes = in.n_ct_in * 2 * L;
-      for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p)});
-      info.fwd_planes += planes;
-    }
-    const uint32_t pplanes = in.n_pt * L;
-    for (uint32_t p = 0; p < pplanes; p += G) tasks.push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p)});
-    info.fwd_planes += pplanes;
-    pjobs[j].n_pre = (uint32_t)(tasks.size() - before);
-  }
-  for (size_t j = 0; j < nj; ++j) {
-    const BJob &bj = b->jobs[j];
-    const uint32_t G = slab_n >> bj.ctx->logN;
-    const uint32_t planes = bj.plan->info.n_ct_out * 2 * bj.ctx->L;
-    for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
-    info.inv_planes += planes;
+  std::vector<PJob> pjobs;
+  he_batch_info info{};
+  he_status bs = build_tables(b->jobs, wsp, b->arith, b->var.slab, tasks, pjobs, info);
+  if (bs != HE_OK) {
+    release(b);
+    return bs;
   }
   b->h_jobs = pjobs;
   b->n_tasks = (uint32_t)tasks.size();
@@ -192,7 +210,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
     release(b);
     return hip_fail(e, "device attribute");
   }
-  const int per_cu = b->slab == 14 ? 1 : 2;
+  const int per_cu = b->var.wg_per_cu;
   b->grid = (uint32_t)std::max(1, std::min<int>(cus * per_cu, (int)std::max<uint32_t>(1u, b->n_tasks)));
   if ((e = hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(PTask))) != hipSuccess ||
       (e = hipMalloc(&b->d_jobs, std::max<size_t>(1, nj) * sizeof(PJob))) != hipSuccess ||
@@ -214,7 +232,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
       release(b);
       return hip_fail(e, "graph capture");
     }
-    hipError_t le = launch_persistent(b->arith, b->slab, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)nj, b->d_ctl,
+    hipError_t le = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)nj, b->d_ctl,
                                       b->ctl_words, b->grid, b->spin_limit, b->strict, b->cap);
     e = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess || e != hipSuccess ||
@@ -230,7 +248,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
 he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job) {
   if (!b || !job) return fail(HE_EINVAL, "null argument");
   if (index >= b->jobs.size()) return fail(HE_EINVAL, "job index");
-  BJob &bj = b->jobs[index];
+  JobRef &bj = b->jobs[index];
   if (job->plan != nullptr && &job->plan->p != bj.plan) return fail(HE_EINVAL, "rebind must keep the plan");
   const uint32_t keep = HE_IN_NTT | HE_PLAIN_POLY;
   if ((job->flags & keep) != (bj.job.flags & keep)) return fail(HE_EINVAL, "rebind must keep the input flags");
@@ -239,8 +257,14 @@ he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job) {
   bj.job = nj;
   if (!b->built) return HE_OK;
   PJob pj;
-  he_status s = fill_job(b, index, pj);
+  std::vector<JobRef> one{bj};
+  std::vector<char *> w{b->ws_ptrs[index]};
+  std::vector<PTask> t;
+  std::vector<PJob> pjs;
+  he_batch_info tmp;
+  he_status s = build_tables(one, w, b->arith, b->var.slab, t, pjs, tmp);
   if (s != HE_OK) return s;
+  pj = pjs[0];
   pj.n_pre = b->h_jobs[index].n_pre;
   b->h_jobs[index] = pj;
   hipError_t e = hipMemcpy(b->d_jobs + index, &pj, sizeof(PJob), hipMemcpyHostToDevice);
@@ -253,7 +277,7 @@ he_status he_batch_run(he_batch *b, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (b->exec) e = hipGraphLaunch(b->exec, st);
-  else e = launch_persistent(b->arith, b->slab, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)b->jobs.size(), b->d_ctl,
+  else e = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)b->jobs.size(), b->d_ctl,
                              b->ctl_words, b->grid, b->spin_limit, b->strict, st);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   return HE_OK;

@@ -1,6 +1,6 @@
 // Device-visible job and task descriptors of the persistent batch kernel.
 #pragma once
-#include "he_internal.hpp"
+#include "plan.hpp"
 
 namespace he {
 
@@ -30,8 +30,28 @@ struct PJob {
   uint32_t pad_;
 };
 
-size_t persistent_lds_bytes(int slab);
-hipError_t launch_persistent(int arith, int slab, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
+// One job as the task-table builder sees it.
+struct JobRef {
+  Ctx *ctx;
+  const Plan *plan;
+  he_job job;
+};
+
+// Device workspace a job needs inside a persistent launch (transformed inputs
+// unless already transformed, transformed plaintexts).
+size_t job_ws_bytes(const JobRef &j);
+// Task table and device job descriptors for `jobs`, with job k's workspace at
+// ws[k].  Every pre task precedes every multiply-accumulate task.
+he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *> &ws, int arith, int slab,
+                       std::vector<PTask> &tasks, std::vector<PJob> &pjobs, he_batch_info &info);
+
+// A compiled variant of the persistent kernel.
+struct PVariant {
+  int arith, slab, loge, logn_min, logn_max;
+  int threads = 0, lds_bytes = 0, wg_per_cu = 1;
+};
+bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, PVariant &v);
+hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
                              uint32_t strict, hipStream_t st);
 

@@ -310,14 +310,28 @@ he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes) 
   return HE_OK;
 }
 
+}  // extern "C"
+
+namespace he {
+size_t layer_ws_bytes(const Ctx &c, const Plan &p, uint32_t flags) { return ws_layout(c, p, flags).total; }
+he_status run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
+                    uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st);
+}  // namespace he
+
+extern "C" {
+
 he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
                          uint32_t flags, void *ws, size_t ws_bytes, void *stream) {
   if (!ctx || !plan || !ct_in || !plain || !ct_out) return fail(HE_EINVAL, "null argument");
   if (plan->ctx != ctx->c) return fail(HE_EINVAL, "plan belongs to another context");
-  const Ctx &c = *ctx->c;
-  const Plan &p = plan->p;
+  return run_layer(*ctx->c, plan->p, ct_in, plain, ct_out, flags, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
+                        uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st) {
   const he_plan_info &in = p.info;
-  hipStream_t st = (hipStream_t)stream;
   const WsLayout L = ws_layout(c, p, flags);
   if (ws_bytes < L.total || (L.total && !ws)) return fail(HE_ENOMEM, "workspace too small");
   char *w = (char *)ws;
@@ -375,6 +389,8 @@ he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in
   }
   return HE_OK;
 }
+
+extern "C" {
 
 he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys) {
   if (!plan || !x || !polys) return fail(HE_EINVAL, "null argument");

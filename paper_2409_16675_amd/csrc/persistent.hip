@@ -69,10 +69,10 @@ struct PMac<ArU64> {
 // One task on one plane group member.  G: geometry with E = 16.  `valid` is
 // false for a group member past the end of the task's plane range: it runs
 // the same barriers but reads zeros and stores nothing.
-template <class A, int LOGN>
+template <class A, int LOGN, int LOGE>
 __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int tid_g, int group,
                                          typename A::V *lds_g) {
-  using G = Geo<LOGN, LOGN - 4>;
+  using G = Geo<LOGN, LOGN - LOGE>;
   using V = typename A::V;
   const uint32_t plane = tk.first + (uint32_t)group;
   const bool valid = plane < tk.first + tk.count;
@@ -172,13 +172,25 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   }
 }
 
-// SLAB = log2 of the coefficients one workgroup holds (14: 1024 threads, one
-// workgroup per CU, ring degrees up to 16384; 13: 512 threads, two per CU,
-// ring degrees up to 8192).  A job's readiness is acquired once per workgroup:
-// after the first acquire (which invalidates this CU's caches after the
-// producers' release) later tasks of the same job read the finished data.
-template <class A, int SLAB>
-__global__ __launch_bounds__(1 << (SLAB - 4), (SLAB == 14 ? 4 : 4)) void k_persistent(
+// SLAB = log2 of the coefficients one workgroup holds per task, LOGE = log2 of
+// the coefficients each thread holds (so a workgroup has 2^(SLAB-LOGE)
+// threads), LOGN_MIN..LOGN_MAX = the ring degrees compiled in.  A batch whose
+// jobs share one ring degree gets a variant with that degree only (smaller
+// code, the register budget of the stand-alone kernels); mixed batches get a
+// variant with every degree.  A job's readiness is acquired once per
+// workgroup: after the first acquire (which invalidates this CU's caches after
+// the producers' release) later tasks of the same job read the finished data.
+template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
+struct PCfg {
+  static constexpr int NT = 1 << (SLAB - LOGE);
+  static constexpr int LDS_BYTES = ((1 << SLAB) + (1 << (SLAB - 5))) * 8;
+  static constexpr int WG_PER_CU = (163840 / (LDS_BYTES + 512)) < 1 ? 1 : (163840 / (LDS_BYTES + 512));
+  static constexpr int MINW = (WG_PER_CU * NT / 256) < 1 ? 1 : (WG_PER_CU * NT / 256 > 8 ? 8 : WG_PER_CU * NT / 256);
+};
+
+template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
+__global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
+                             (PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::MINW)) void k_persistent(
     const PTask *__restrict__ tasks, uint32_t n_tasks, const PJob *__restrict__ jobs, uint32_t n_jobs,
     uint32_t *__restrict__ ctl, uint32_t spin_limit, uint32_t strict) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -189,20 +201,23 @@ __global__ __launch_bounds__(1 << (SLAB - 4), (SLAB == 14 ? 4 : 4)) void k_persi
   uint32_t *head = ctl + CTL_HEAD, *err = ctl + CTL_ERR, *done = ctl + CTL_DONE;
   if (tid == 0)
     for (int k = 0; k < 64; ++k) s_ready[k] = 0u;
-  // The launch may be a graph replay whose dispatch does not invalidate this XCD's
-  // L2: drop any line cached before the launch (inputs written by copies or by
-  // kernels on other XCDs) before reading anything.
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+  // (The caches are invalidated before the launch and written back after it by
+  // k_edge_fence, see launch_persistent.)
+  // thread 0 keeps the index of the following task in flight while the current
+  // one runs, so the queue atomic's latency is hidden
+  uint32_t next = 0;
+  if (tid == 0) next = atomicAdd(head, 1u);
   for (;;) {
     // thread 0 takes the next task and decides, for the whole workgroup, whether
     // it must wait for the job's pre tasks (so every thread takes the same branch)
     if (tid == 0) {
-      const uint32_t t0 = atomicAdd(head, 1u);
+      const uint32_t t0 = next;
+      if (t0 < n_tasks) next = atomicAdd(head, 1u);
       uint32_t w = 0;
       if (t0 < n_tasks) {
         const PTask k0 = tasks[t0];
         if (k0.kind == PT_MAC_INV && jobs[k0.job].n_pre)
-          w = (!strict && k0.job < 2048 && ((s_ready[k0.job >> 5] >> (k0.job & 31)) & 1u)) ? 0u : 1u;
+          w = (!(strict & 1u) && k0.job < 2048 && ((s_ready[k0.job >> 5] >> (k0.job & 31)) & 1u)) ? 0u : 1u;
       }
       s_task = t0;
       s_wait = w;
@@ -224,39 +239,42 @@ __global__ __launch_bounds__(1 << (SLAB - 4), (SLAB == 14 ? 4 : 4)) void k_persi
             break;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (strict & 4u) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (tk.job < 2048) s_ready[tk.job >> 5] |= 1u << (tk.job & 31);
       }
       __syncthreads();
-      if (strict) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (strict & 1u) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     const int logn = (int)jb.logN;
-    const int logt = logn - 4;
+    const int logt = logn - LOGE;
     const int group = tid >> logt;
     const int tid_g = tid & ((1 << logt) - 1);
     const int words = (1 << logn) + (1 << (logn - 5));
     typename A::V *lds_g = lds + (size_t)group * words;
-    switch (logn) {
-      case 10: run_task<A, 10>(tk, jb, tid_g, group, lds_g); break;
-      case 11: run_task<A, 11>(tk, jb, tid_g, group, lds_g); break;
-      case 12: run_task<A, 12>(tk, jb, tid_g, group, lds_g); break;
-      case 13: run_task<A, 13>(tk, jb, tid_g, group, lds_g); break;
-      default:
-        if constexpr (SLAB >= 14) run_task<A, 14>(tk, jb, tid_g, group, lds_g);
-        break;
+    if constexpr (LOGN_MIN == LOGN_MAX) {
+      run_task<A, LOGN_MIN, LOGE>(tk, jb, tid_g, group, lds_g);
+    } else {
+      switch (logn) {
+        case 10: if constexpr (LOGN_MIN <= 10) run_task<A, 10, LOGE>(tk, jb, tid_g, group, lds_g); break;
+        case 11: if constexpr (LOGN_MIN <= 11) run_task<A, 11, LOGE>(tk, jb, tid_g, group, lds_g); break;
+        case 12: run_task<A, 12, LOGE>(tk, jb, tid_g, group, lds_g); break;
+        case 13: run_task<A, 13, LOGE>(tk, jb, tid_g, group, lds_g); break;
+        default:
+          if constexpr (LOGN_MAX >= 14) run_task<A, 14, LOGE>(tk, jb, tid_g, group, lds_g);
+          break;
+      }
     }
     if (tk.kind != PT_MAC_INV) {
       // every wave waits until its own global stores have reached L2 (the barrier
       // alone orders LDS only); thread 0's release then writes L2 back and publishes
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-      if (strict) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (strict & 1u) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();
     if (tk.kind != PT_MAC_INV && tid == 0)
       __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // write this workgroup's outputs back from L2 before the launch ends (same reason)
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 }
 
 // Zero the queue head, the error flag and the per-job counters (a kernel, not a
@@ -265,35 +283,78 @@ __global__ void k_reset_ctl(uint32_t *ctl, uint32_t n_words) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_words; k += gridDim.x * blockDim.x) ctl[k] = 0u;
 }
 
-size_t persistent_lds_bytes(int slab) { return (size_t)((1 << slab) + (1 << (slab - 5))) * 8; }
+// Cache maintenance around a persistent launch, which may be a graph replay whose
+// dispatch neither invalidates nor writes back the XCD L2 caches: before it,
+// every XCD drops lines cached earlier (inputs rewritten by copies or by kernels
+// on other XCDs); after it, every XCD writes its dirty lines back.  Workgroups
+// are dealt round-robin over the XCDs, so 64 of them reach all eight.
+__global__ void k_edge_fence(int release) {
+  if (threadIdx.x == 0) {
+    if (release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+  }
+}
 
-template <class A, int SLAB>
+template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
 static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const PJob *jobs, uint32_t n_jobs, uint32_t *ctl,
                            uint32_t grid, uint32_t spin_limit, uint32_t strict, hipStream_t st) {
-  const size_t lds = persistent_lds_bytes(SLAB);
+  using C = PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>;
   static bool set = false;
   if (!set) {
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_persistent<A, SLAB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_persistent<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
     if (e != hipSuccess) return e;
     set = true;
   }
-  hipLaunchKernelGGL((k_persistent<A, SLAB>), dim3(grid), dim3(1 << (SLAB - 4)), lds, st, tasks, n_tasks, jobs, n_jobs,
-                     ctl, spin_limit, strict);
+  hipLaunchKernelGGL((k_persistent<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>), dim3(grid), dim3(C::NT), C::LDS_BYTES, st,
+                     tasks, n_tasks, jobs, n_jobs, ctl, spin_limit, strict);
   return hipGetLastError();
 }
 
-hipError_t launch_persistent(int arith, int slab, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
+// Variants compiled: F64 single-degree 4096/8192/16384 with 32 coefficients per
+// thread, and mixed-degree variants (16 per thread) for both arithmetics.
+bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, PVariant &v) {
+  if (arith == HE_ARITH_F64 && logn_min == logn_max && logn_min >= 12 && logn_min <= 14) {
+    v = PVariant{arith, (int)logn_min, 5, (int)logn_min, (int)logn_min};
+  } else if (logn_max <= 13) {
+    v = PVariant{arith, 13, 4, 10, 13};
+  } else {
+    v = PVariant{arith, 14, 4, 10, 14};
+  }
+  v.threads = 1 << (v.slab - v.loge);
+  v.lds_bytes = ((1 << v.slab) + (1 << (v.slab - 5))) * 8;
+  v.wg_per_cu = 163840 / (v.lds_bytes + 512);
+  if (v.wg_per_cu < 1) v.wg_per_cu = 1;
+  return true;
+}
+
+hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
                              uint32_t strict, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ctl, ctl_words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (arith == HE_ARITH_F64)
-    return slab == 14 ? launch_p<ArF64, 14>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
-                      : launch_p<ArF64, 13>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st);
-  return slab == 14 ? launch_p<ArU64, 14>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
-                    : launch_p<ArU64, 13>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st);
+  if (!(strict & 8u)) {
+    hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+#define HE_P(A, S, E, MN, MX) launch_p<A, S, E, MN, MX>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
+  if (v.arith == HE_ARITH_F64) {
+    if (v.slab == 12 && v.loge == 5) e = HE_P(ArF64, 12, 5, 12, 12);
+    else if (v.slab == 13 && v.loge == 5) e = HE_P(ArF64, 13, 5, 13, 13);
+    else if (v.slab == 14 && v.loge == 5) e = HE_P(ArF64, 14, 5, 14, 14);
+    else if (v.slab == 13) e = HE_P(ArF64, 13, 4, 10, 13);
+    else e = HE_P(ArF64, 14, 4, 10, 14);
+  } else {
+    e = v.slab == 13 ? HE_P(ArU64, 13, 4, 10, 13) : HE_P(ArU64, 14, 4, 10, 14);
+  }
+#undef HE_P
+  if (e != hipSuccess) return e;
+  if (!(strict & 8u)) {
+    hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 1);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace he

@@ -80,6 +80,13 @@ _SIGS = {
     "he_batch_sync": [c_void_p, c_void_p],
     "he_batch_get_info": [c_void_p, c_void_p],
     "he_batch_destroy": [c_void_p],
+    "he_server_create": [c_void_p, ctypes.POINTER(c_void_p)],
+    "he_server_submit": [c_void_p, c_void_p, c_void_p, c_u64, c_u32, ctypes.POINTER(c_u64)],
+    "he_server_wait": [c_void_p, c_u64, ctypes.c_int64, c_void_p],
+    "he_server_drain": [c_void_p],
+    "he_server_replay": [c_void_p, c_u32, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p],
+    "he_server_stats": [c_void_p, c_void_p],
+    "he_server_destroy": [c_void_p],
 }
 for _n, _a in _SIGS.items():
     _f = getattr(_lib, _n)
@@ -356,6 +363,77 @@ def he_batch_get_info(b):
 
 def he_batch_destroy(b):
     _chk(_lib.he_batch_destroy(b), "he_batch_destroy")
+
+
+# ------------------------------------------------------------------ serving
+HE_SERVE_CONTINUOUS, HE_SERVE_SEQUENTIAL = 0, 1
+HE_SERVE_KEEP_RESIDENT = 0x1
+
+
+class he_server_params(ctypes.Structure):
+    _fields_ = [("device", c_i32), ("mode", c_u32), ("mem_cap_bytes", c_u64), ("arena_bytes", c_u64),
+                ("max_batch_jobs", c_u32), ("slots", c_u32), ("session_jobs", c_u32), ("poll_us", c_u32)]
+
+
+class he_job_result(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double)]
+
+
+class he_server_info(ctypes.Structure):
+    _fields_ = [("completed", c_u64), ("rejected", c_u64), ("epochs", c_u64), ("mean_jobs_per_epoch", ctypes.c_double),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("span_s", ctypes.c_double), ("peak_bytes", c_u64),
+                ("in_use_bytes", c_u64)]
+
+
+def he_server_create(mem_cap_bytes=64 << 30, mode=HE_SERVE_CONTINUOUS, device=0, arena_bytes=0, max_batch_jobs=0,
+                     slots=0, session_jobs=0, poll_us=0):
+    p = he_server_params(device, mode, mem_cap_bytes, arena_bytes, max_batch_jobs, slots, session_jobs, poll_us)
+    h = c_void_p()
+    _chk(_lib.he_server_create(ctypes.byref(p), ctypes.byref(h)), "he_server_create")
+    return h
+
+
+def he_server_submit(s, ctx, plan, ct_in, plain, ct_out, flags=0, session=0, submit_flags=0):
+    j = _job(plan, ct_in, plain, ct_out, flags)
+    t = c_u64()
+    _chk(_lib.he_server_submit(s, ctx, ctypes.byref(j), session, submit_flags, ctypes.byref(t)), "he_server_submit")
+    return t.value
+
+
+def he_server_wait(s, ticket, timeout_us=-1):
+    r = he_job_result()
+    st = _lib.he_server_wait(s, ticket, timeout_us, ctypes.byref(r))
+    _chk(st, "he_server_wait")
+    return dict(status=r.status, latency_s=r.latency_s, queue_s=r.queue_s)
+
+
+def he_server_drain(s):
+    _chk(_lib.he_server_drain(s), "he_server_drain")
+
+
+def he_server_replay(s, ctxs, jobs, arrival_s, sessions=None, submit_flags=0):
+    """jobs: list of (plan, ct_in, plain, ct_out, flags); returns per-job latency (s)."""
+    n = len(jobs)
+    ctx_arr = (c_void_p * n)(*[c.value if isinstance(c, c_void_p) else c for c in ctxs])
+    job_arr = (he_job * n)(*[_job(*j) for j in jobs])
+    arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    ses = None if sessions is None else np.ascontiguousarray(sessions, dtype=np.uint64)
+    lat = np.zeros(n, dtype=np.float64)
+    _chk(_lib.he_server_replay(s, n, ctypes.cast(ctx_arr, c_void_p), ctypes.cast(job_arr, c_void_p),
+                               arr.ctypes.data_as(c_void_p), None if ses is None else ses.ctypes.data_as(c_void_p),
+                               submit_flags, lat.ctypes.data_as(c_void_p)), "he_server_replay")
+    return lat
+
+
+def he_server_stats(s):
+    i = he_server_info()
+    _chk(_lib.he_server_stats(s, ctypes.byref(i)), "he_server_stats")
+    return {n: getattr(i, n) for n, _ in he_server_info._fields_}
+
+
+def he_server_destroy(s):
+    _chk(_lib.he_server_destroy(s), "he_server_destroy")
 
 
 # ------------------------------------------------------------------ helpers
