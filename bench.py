@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference for hardware byte counters)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -176,6 +179,66 @@ def roofline_persistent(wl, kern_ms, binfo):
             "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
 
 
+def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4):
+    """Poisson arrivals (mean `rate` jobs/s) drawn from the uneven layer mix, sessions of 6
+    jobs whose transformed inputs stay resident, 64 GB admission cap; continuous batching
+    against the sequential per-layer server on the same trace."""
+    import numpy as np
+    ctxs = {(N, L): he.Context(N, L) for N, L in synth.MIX_RINGS}
+    kinds = {}
+    for li, spec in enumerate(synth.MIX_LAYERS):
+        for ri, (N, L) in enumerate(synth.MIX_RINGS):
+            ctx = ctxs[(N, L)]
+            if spec[0] == "conv":
+                _, C, M, H, W, h, P = spec
+                plan = he.Plan(ctx, he.HE_KIND_CONV, B=1, C=C, M=M, H=H, W=W, h=h, P=P)
+                w = synth.int8_uniform(synth.rng(5, synth.STREAM_PT, li), (M, C, h, h))
+            else:
+                _, n_in, n_out = spec
+                plan = he.Plan(ctx, he.HE_KIND_FC, B=1, n_in=n_in, n_out=n_out)
+                w = synth.int8_uniform(synth.rng(5, synth.STREAM_PT, li), (n_out, n_in))
+            info = plan.info
+            g = synth.rng(5, synth.STREAM_CT, 10 * li + ri)
+            bufs = [(he.to_device_u64(synth.uniform_residues(g, (info["n_ct_in"], 2), ctx.q, N)),
+                     he.empty_u64((info["n_ct_out"], 2, L, N))) for _ in range(copies)]
+            kinds[(li, ri)] = dict(ctx=ctx, plan=plan, w=torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda(),
+                                   bufs=bufs, cpmul=info["n_terms"])
+    mix = synth.job_mix(n_jobs, workload=5)
+    arr = synth.poisson_arrivals(n_jobs, rate)
+    arr = arr - arr[0]
+    jobs, ctx_list, cpmul = [], [], 0
+    for k, (li, ri) in enumerate(mix):
+        kd = kinds[(li, ri)]
+        ct, out = kd["bufs"][k % copies]
+        jobs.append((kd["plan"].h, ct, kd["w"], out, 0))
+        ctx_list.append(kd["ctx"].h)
+        cpmul += kd["cpmul"]
+    sessions = np.arange(n_jobs, dtype=np.uint64) // 6 + 1
+    res = {"rate_jobs_per_s": rate, "jobs": n_jobs, "mix": "uneven 5-layer x 3-ring mix, batch 1",
+           "session_jobs": 6, "cap_GB": 64}
+    for name, mode in (("continuous", he.HE_SERVE_CONTINUOUS), ("sequential", he.HE_SERVE_SEQUENTIAL)):
+        srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
+                                  max_batch_jobs=64, session_jobs=6)
+        # warm the kernels and the arena with a short burst
+        he.he_server_replay(srv, ctx_list[:32], jobs[:32], np.zeros(32))
+        he.he_server_destroy(srv)
+        srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
+                                  max_batch_jobs=64, session_jobs=6)
+        t0 = time.perf_counter()
+        lat = he.he_server_replay(srv, ctx_list, jobs, arr, sessions, he.HE_SERVE_KEEP_RESIDENT)
+        wall = time.perf_counter() - t0
+        st = he.he_server_stats(srv)
+        he.he_server_destroy(srv)
+        res[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                     "throughput_jobs_per_s": round(n_jobs / st["span_s"], 1),
+                     "cpmul_per_s": round(cpmul / st["span_s"], 1),
+                     "epochs": st["epochs"], "mean_jobs_per_epoch": round(st["mean_jobs_per_epoch"], 2),
+                     "peak_footprint_GB": round(st["peak_bytes"] / 2 ** 30, 3), "wall_s": round(wall, 3)}
+    return res
+
+
 def cpu_baseline(wl, he):
     """The oracle (C, one transform per input plane, OpenMP over planes) on the same batch."""
     import numpy as np
@@ -235,6 +298,15 @@ def main():
         "roofline_fused_mac_inv": roofline(wl, stats),
     }
     he.he_batch_destroy(batch)
+    if args.calib_copy:
+        src = torch.empty(64 << 20, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = src.numel() * 8
+    if not args.no_serve:
+        res["serving"] = serving(he, torch, synth)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(wl, he)
     print(json.dumps(res))

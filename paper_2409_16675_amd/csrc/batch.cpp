@@ -18,6 +18,7 @@ struct he_batch {
   uint32_t *d_ctl = nullptr;
   uint32_t n_tasks = 0, ctl_words = 0, grid = 0;
   he::PVariant var{};
+  he::XQ xq{};
   uint32_t strict = 0;
   std::vector<he::PJob> h_jobs;
   std::vector<char *> ws_ptrs;
@@ -25,7 +26,7 @@ struct he_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   he_batch_info info{};
-  uint32_t spin_limit = 1u << 24;
+  uint32_t spin_limit = he::kSpinLimit;
 };
 
 using namespace he;
@@ -99,7 +100,8 @@ static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
 }
 
 he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *> &ws, int arith, int slab,
-                       std::vector<PTask> &tasks, std::vector<PJob> &pjobs, he_batch_info &info) {
+                       std::vector<PTask> &tasks, std::vector<PJob> &pjobs, he_batch_info &info,
+                       uint32_t xq[kXcds + 1]) {
   const size_t nj = jobs.size();
   const uint32_t slab_n = 1u << slab;
   tasks.clear();
@@ -124,6 +126,7 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
     pjobs[j].n_pre = (uint32_t)(tasks.size() - before);
     info.cpmul += in.n_terms;
   }
+  const uint32_t n_pre = (uint32_t)tasks.size();
   for (size_t j = 0; j < nj; ++j) {
     const JobRef &bj = jobs[j];
     const uint32_t G = slab_n >> bj.ctx->logN;
@@ -131,6 +134,10 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
     for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
     info.inv_planes += planes;
   }
+  // dependent tasks, in output order, cut into kXcds contiguous queues: outputs
+  // that share inputs land on one XCD and share its L2
+  const uint32_t n_dep = (uint32_t)tasks.size() - n_pre;
+  for (int x = 0; x <= kXcds; ++x) xq[x] = n_pre + (uint32_t)(((uint64_t)n_dep * x) / kXcds);
   info.n_jobs = (uint32_t)nj;
   info.n_tasks = (uint32_t)tasks.size();
   info.arith = (uint32_t)arith;
@@ -165,7 +172,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   release(b);
   hipError_t e = hipSetDevice(b->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  b->strict = ((flags & HE_BATCH_STRICT_SYNC) ? 1u : 0u) | ((flags >> 8) & 0xCu);   // bits 10, 11: timing probes
+  b->strict = (flags & HE_BATCH_STRICT_SYNC) ? 1u : 0u;
   bool all_f64 = true;
   uint32_t max_logn = 10, min_logn = 14;
   for (auto &j : b->jobs) {
@@ -196,7 +203,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   std::vector<PTask> tasks;
   std::vector<PJob> pjobs;
   he_batch_info info{};
-  he_status bs = build_tables(b->jobs, wsp, b->arith, b->var.slab, tasks, pjobs, info);
+  he_status bs = build_tables(b->jobs, wsp, b->arith, b->var.slab, tasks, pjobs, info, b->xq.b);
   if (bs != HE_OK) {
     release(b);
     return bs;
@@ -232,7 +239,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
       release(b);
       return hip_fail(e, "graph capture");
     }
-    hipError_t le = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)nj, b->d_ctl,
+    hipError_t le = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->xq, b->d_jobs, (uint32_t)nj, b->d_ctl,
                                       b->ctl_words, b->grid, b->spin_limit, b->strict, b->cap);
     e = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess || e != hipSuccess ||
@@ -262,7 +269,8 @@ he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job) {
   std::vector<PTask> t;
   std::vector<PJob> pjs;
   he_batch_info tmp;
-  he_status s = build_tables(one, w, b->arith, b->var.slab, t, pjs, tmp);
+  uint32_t xq_tmp[kXcds + 1];
+  he_status s = build_tables(one, w, b->arith, b->var.slab, t, pjs, tmp, xq_tmp);
   if (s != HE_OK) return s;
   pj = pjs[0];
   pj.n_pre = b->h_jobs[index].n_pre;
@@ -277,7 +285,7 @@ he_status he_batch_run(he_batch *b, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (b->exec) e = hipGraphLaunch(b->exec, st);
-  else e = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->d_jobs, (uint32_t)b->jobs.size(), b->d_ctl,
+  else e = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->xq, b->d_jobs, (uint32_t)b->jobs.size(), b->d_ctl,
                              b->ctl_words, b->grid, b->spin_limit, b->strict, st);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   return HE_OK;

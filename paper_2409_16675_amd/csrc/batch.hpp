@@ -7,8 +7,14 @@ namespace he {
 enum PTaskKind : uint32_t { PT_FWD_CT = 0, PT_PT = 1, PT_MAC_INV = 2 };
 enum PlainKind : uint32_t { PK_CONV = 0, PK_FC = 1, PK_POLY = 2 };
 
-// control words: queue head, error flag, then one completion counter per job
-enum : uint32_t { CTL_HEAD = 0, CTL_ERR = 1, CTL_DONE = 64 };
+// control words: pre-task queue head, error flag, one head per XCD queue of
+// dependent tasks (each on its own 128-byte line), then one completion counter
+// per job
+enum : uint32_t { CTL_HEAD = 0, CTL_ERR = 1, CTL_XQ = 32, CTL_DONE = 32 + 8 * 32 };
+constexpr int kXcds = 8;
+// polls of a dependency counter before a waiting workgroup gives up and raises
+// the error flag (about 1 s at the longest back-off)
+constexpr uint32_t kSpinLimit = 1u << 20;
 
 struct PTask {
   uint32_t kind, job, first, count;   // planes [first, first + count) of the job's array
@@ -42,8 +48,11 @@ struct JobRef {
 size_t job_ws_bytes(const JobRef &j);
 // Task table and device job descriptors for `jobs`, with job k's workspace at
 // ws[k].  Every pre task precedes every multiply-accumulate task.
+// Dependent tasks are split into kXcds contiguous queues, [xq[x], xq[x+1]) in
+// the task table, one per XCD; pre tasks are [0, xq[0]).
 he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *> &ws, int arith, int slab,
-                       std::vector<PTask> &tasks, std::vector<PJob> &pjobs, he_batch_info &info);
+                       std::vector<PTask> &tasks, std::vector<PJob> &pjobs, he_batch_info &info,
+                       uint32_t xq[kXcds + 1]);
 
 // A compiled variant of the persistent kernel.
 struct PVariant {
@@ -51,7 +60,10 @@ struct PVariant {
   int threads = 0, lds_bytes = 0, wg_per_cu = 1;
 };
 bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, PVariant &v);
-hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
+struct XQ {
+  uint32_t b[kXcds + 1];   // queue bounds in the task table
+};
+hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
                              uint32_t strict, hipStream_t st);
 

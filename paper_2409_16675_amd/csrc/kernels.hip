@@ -2,6 +2,7 @@
 // transform, plaintext packing, and the small helpers used by encryption.
 #include "he_internal.hpp"
 #include "ntt.hpp"
+#include "mac.hpp"
 
 namespace he {
 
@@ -79,47 +80,9 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
 }
 
 // ------------------------------------------------- multiply-accumulate (slots)
-// Sum over a term list of slot-wise products, returned as a policy value with
-// bound A::kReduced (F64) or canonical (U64).
-template <class A>
-struct MacAcc;
-
-// fp64: each product has |p| <= 0.76 q; after a fold |acc| <= 0.51 q, so a chunk
-// of 8 products keeps |acc| <= 6.6 q < 7 q.
-template <>
-struct MacAcc<ArF64> {
-  static constexpr int kChunk = 8;
-  double acc = 0.0;
-  __device__ __forceinline__ void init(const PrimeK *) {}
-  __device__ __forceinline__ void add(const ArF64 &ar, uint64_t a, uint64_t b) { acc += ar.mulv((double)a, (double)b); }
-  __device__ __forceinline__ void fold(const ArF64 &ar) { acc = ar.reduce(acc); }
-  __device__ __forceinline__ double value() const { return acc; }
-};
-
-// integer: 128-bit sums of products < 2^124; a folded value (< q) plus 15
-// products stays below 2^128.  fold: hi * (2^64 mod q) + lo, canonical.
-template <>
-struct MacAcc<ArU64> {
-  static constexpr int kChunk = 15;
-  uint64_t lo = 0, hi = 0;
-  const PrimeK *pk = nullptr;
-  __device__ __forceinline__ void init(const PrimeK *p) { pk = p; }
-  __device__ __forceinline__ void add(const ArU64 &, uint64_t a, uint64_t b) {
-    const uint64_t pl = a * b, ph = __umul64hi(a, b);
-    const uint64_t nl = lo + pl;
-    hi += ph + (nl < lo ? 1u : 0u);
-    lo = nl;
-  }
-  __device__ __forceinline__ void fold(const ArU64 &ar) {
-    uint64_t x = ar.mul(hi, pk->r64, pk->r64s) + ar.mul(lo, 1, pk->one_s);   // < 4q
-    x = x >= ar.two_q ? x - ar.two_q : x;
-    x = x >= ar.q ? x - ar.q : x;
-    lo = x;
-    hi = 0;
-  }
-  __device__ __forceinline__ uint64_t value() const { return lo; }
-};
-
+// Term lists: output o sums the terms row[o] .. row[o+1]-1, term t pairing
+// ciphertext cti[t] with plaintext pti[t]; with row == nullptr there is one
+// output whose terms pair ciphertext t with plaintext t, t < K.
 struct TermArgs {
   const int32_t *row, *cti, *pti;
   uint32_t K;     // identity mode (row == nullptr): one output, terms 0..K-1
@@ -142,11 +105,15 @@ __device__ __forceinline__ int term_pt(const TermArgs &ta, int t) { return ta.ro
 template <class A, int LOGN, int LOGT, bool ACC>
 __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_mac_inv(
     uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat, const uint64_t *__restrict__ pt_hat, TermArgs ta,
-    const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, int L) {
+    const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, int L, uint32_t xcd_chunk,
+    int n_planes) {
   using G = Geo<LOGN, LOGT>;
   extern __shared__ __align__(16) unsigned char smem[];
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
-  const int plane = blockIdx.x;   // (o * 2 + comp) * L + i
+  // Workgroups are dealt round-robin over the 8 XCDs; give XCD x a contiguous
+  // run of output planes so that outputs sharing inputs share that XCD's L2.
+  const int plane = (int)((blockIdx.x & 7u) * xcd_chunk + (blockIdx.x >> 3));   // (o * 2 + comp) * L + i
+  if (plane >= n_planes) return;
   const int i = plane % L;
   const int comp = (plane / L) & 1;
   const int o = plane / (2 * L);
@@ -156,21 +123,15 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
   int t0, t1;
   term_range(ta, o, t0, t1);
   MacAcc<A> acc[G::E];
-#pragma unroll
-  for (int j = 0; j < G::E; ++j) acc[j].init(pk);
   for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
     const int te = min(t + MacAcc<A>::kChunk, t1);
     for (int tt = t; tt < te; ++tt) {
       const uint64_t *a = ct_hat + ((size_t)(term_ct(ta, tt) * 2 + comp) * L + i) * G::N;
       const uint64_t *b = pt_hat + ((size_t)term_pt(ta, tt) * L + i) * G::N;
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) {
-        const int k = j * G::NT + tid;
-        acc[j].add(ar, a[k], b[k]);
-      }
+      mac_term<A, G::E, G::NT>(ar, acc, a, b, tid);
     }
 #pragma unroll
-    for (int j = 0; j < G::E; ++j) acc[j].fold(ar);
+    for (int j = 0; j < G::E; ++j) acc[j].fold(ar, *pk);
   }
 #pragma unroll
   for (int j = 0; j < G::E; ++j) lds[lpad(j * G::NT + tid)] = acc[j].value();
@@ -201,7 +162,6 @@ __global__ __launch_bounds__(256) void k_mac_slots(uint64_t *__restrict__ out, c
   int t0, t1;
   term_range(ta, o, t0, t1);
   MacAcc<A> acc;
-  acc.init(pk);
   for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
     const int te = min(t + MacAcc<A>::kChunk, t1);
     for (int tt = t; tt < te; ++tt) {
@@ -209,7 +169,7 @@ __global__ __launch_bounds__(256) void k_mac_slots(uint64_t *__restrict__ out, c
       const uint64_t b = pt_hat[((size_t)term_pt(ta, tt) * L + i) * N + k];
       acc.add(ar, a, b);
     }
-    acc.fold(ar);
+    acc.fold(ar, *pk);
   }
   uint64_t v = ar.store(acc.value());
   uint64_t *dst = out + (size_t)plane * N + k;
@@ -389,17 +349,20 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
       hipLaunchKernelGGL((k_ntt_inv<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, c.d_primes,
                          tw_ptr<A>(c, true), (int)c.L);
       break;
-    case OP_MAC_INV:
+    case OP_MAC_INV: {
+      const uint32_t chunk = (la.grid + 7) / 8;
+      const unsigned grid = chunk * 8;
       if (la.accumulate) {
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, true>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, true>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
-                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L);
+        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, true>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
+                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
       } else {
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, false>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
-                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L);
+        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
+                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
       }
       break;
+    }
   }
   return hipGetLastError();
 }

@@ -1,0 +1,67 @@
+// Slot-wise multiply-accumulate in the transformed domain (the CPMul products of
+// ciphertext and plaintext slots summed into an output ciphertext, Sec. 3.2 and
+// Sec. 3.3): acc[k] = sum_t ct_t[k] * pt_t[k] mod q, shared by the fused
+// multiply-accumulate + inverse-transform kernel and the persistent kernel.
+#pragma once
+#include "arith.hpp"
+
+namespace he {
+
+template <class A>
+struct MacAcc;
+
+// fp64: each product has |p| <= 0.76 q; after a fold |acc| <= 0.51 q, so a chunk
+// of 8 products keeps |acc| <= 6.6 q < 7 q.
+template <>
+struct MacAcc<ArF64> {
+  static constexpr int kChunk = 8;
+  static constexpr int kLoadBatch = 32;   // coefficients whose operands are loaded together
+  double acc = 0.0;
+  __device__ __forceinline__ void add(const ArF64 &ar, uint64_t a, uint64_t b) { acc += ar.mulv(ar.load(a), ar.load(b)); }
+  __device__ __forceinline__ void fold(const ArF64 &ar, const PrimeK &) { acc = ar.reduce(acc); }
+  __device__ __forceinline__ double value() const { return acc; }
+};
+
+// integer: 128-bit sums of products < 2^124; a folded value (< q) plus 15
+// products stays below 2^128.  fold: hi * (2^64 mod q) + lo, canonical.
+template <>
+struct MacAcc<ArU64> {
+  static constexpr int kChunk = 15;
+  static constexpr int kLoadBatch = 8;    // the 128-bit accumulators leave fewer registers
+  uint64_t lo = 0, hi = 0;
+  __device__ __forceinline__ void add(const ArU64 &, uint64_t a, uint64_t b) {
+    const uint64_t pl = a * b, ph = __umul64hi(a, b);
+    const uint64_t nl = lo + pl;
+    hi += ph + (nl < lo ? 1u : 0u);
+    lo = nl;
+  }
+  __device__ __forceinline__ void fold(const ArU64 &ar, const PrimeK &pk) {
+    uint64_t x = ar.mul(hi, pk.r64, pk.r64s) + ar.mul(lo, 1, pk.one_s);   // < 4q
+    x = x >= ar.two_q ? x - ar.two_q : x;
+    x = x >= ar.q ? x - ar.q : x;
+    lo = x;
+    hi = 0;
+  }
+  __device__ __forceinline__ uint64_t value() const { return lo; }
+};
+
+// One term for the E coefficients j * NT + tid of a thread: the operand loads
+// of a batch of coefficients are all issued before its first product, so they
+// are in flight together instead of one memory round trip per coefficient.
+template <class A, int E, int NT, class P>
+__device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, int tid) {
+  constexpr int B = E < MacAcc<A>::kLoadBatch ? E : MacAcc<A>::kLoadBatch;
+#pragma unroll
+  for (int j0 = 0; j0 < E; j0 += B) {
+    uint64_t va[B], vb[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      va[j] = a[(j0 + j) * NT + tid];
+      vb[j] = b[(j0 + j) * NT + tid];
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j0 + j].add(ar, va[j], vb[j]);
+  }
+}
+
+}  // namespace he

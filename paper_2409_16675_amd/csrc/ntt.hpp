@@ -33,6 +33,28 @@ struct Geo {
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 
+// Pointers read from memory (job tables) are generic; qualifying them as global
+// lets the compiler use global (not flat) loads and stores, which do not tie the
+// memory counters to LDS traffic.
+#define HE_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ HE_GLOBAL T *as_global(T *p) {
+  return (HE_GLOBAL T *)p;
+}
+
+// One twiddle entry (16 bytes) through a generic or a global pointer.
+template <class Tw>
+__device__ __forceinline__ Tw load_tw(const Tw *tw, int idx) {
+  return tw[idx];
+}
+template <class Tw>
+__device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, int idx) {
+  typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+  static_assert(sizeof(Tw) == sizeof(u64x2), "twiddle entries are 16 bytes");
+  const u64x2 v = *(const HE_GLOBAL u64x2 *)(tw + idx);
+  return __builtin_bit_cast(Tw, v);
+}
+
 // Waves per SIMD two (or more) resident workgroups need, given the LDS a plane
 // takes: passed as the second __launch_bounds__ argument so that the compiler
 // keeps the register count low enough for that occupancy.
@@ -205,8 +227,8 @@ __device__ __forceinline__ typename A::V reduce_gs_in(const A &ar, typename A::V
 
 // ------------------------------------------------------------------------ passes
 // Forward pass K.  `ld(i)` yields the value at plane index i, `st(i, v)` stores it.
-template <class A, class G, int K, class Ld, class St>
-__device__ __forceinline__ void fwd_pass(const A &ar, const typename A::Tw *__restrict__ tw, int tid, Ld ld, St st) {
+template <class A, class G, int K, class TwP, class Ld, class St>
+__device__ __forceinline__ void fwd_pass(const A &ar, TwP tw, int tid, Ld ld, St st) {
   using V = typename A::V;
   constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
   constexpr PassPlan pp = plan_ct<A>(R, fwd_bound_in<A, G>(K));
@@ -230,7 +252,7 @@ __device__ __forceinline__ void fwd_pass(const A &ar, const typename A::Tw *__re
       for (int p = 0; p < (1 << R); ++p) {
         if (p & (1 << (R - 1 - u))) continue;
         const int p2 = p | (1 << (R - 1 - u));
-        const typename A::Tw w = tw[(1 << s) + ((high << u) | (p >> (R - u)))];
+        const typename A::Tw w = load_tw(tw, (1 << s) + ((high << u) | (p >> (R - u))));
         ar.ct(v[(g << R) | p], v[(g << R) | p2], w);
       }
     }
@@ -242,8 +264,8 @@ __device__ __forceinline__ void fwd_pass(const A &ar, const typename A::Tw *__re
 }
 
 // Inverse pass K (stages S0+R-1 down to S0).  B0 is the bound of the transform's input.
-template <class A, class G, int K, int B0X100, class Ld, class St>
-__device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__restrict__ tw, int tid, Ld ld, St st) {
+template <class A, class G, int K, int B0X100, class TwP, class Ld, class St>
+__device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St st) {
   using V = typename A::V;
   constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
   constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
@@ -268,9 +290,9 @@ __device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__re
         if (p & (1 << (R - 1 - u))) continue;
         const int p2 = p | (1 << (R - 1 - u));
         if (s == 0) {
-          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], tw[0], tw[1]);
+          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], load_tw(tw, 0), load_tw(tw, 1));
         } else {
-          const typename A::Tw w = tw[(1 << s) + ((high << u) | (p >> (R - u)))];
+          const typename A::Tw w = load_tw(tw, (1 << s) + ((high << u) | (p >> (R - u))));
           gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], w);
         }
       }
@@ -289,9 +311,8 @@ __device__ __forceinline__ void inv_pass(const A &ar, const typename A::Tw *__re
 // sharing LDS need only one barrier between them.
 
 // Forward passes K..NPASS-1, LDS to LDS.
-template <class A, class G, int K>
-__device__ __forceinline__ void fwd_lds_passes(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
-                                               typename A::V *lds) {
+template <class A, class G, int K, class TwP>
+__device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds) {
   if constexpr (K < G::NPASS) {
     __syncthreads();
     auto ld = [&](int i) { return lds[lpad(i)]; };
@@ -302,9 +323,8 @@ __device__ __forceinline__ void fwd_lds_passes(const A &ar, const typename A::Tw
 }
 
 // Inverse passes K down to 1, LDS to LDS (pass 0 is run by the caller, to HBM).
-template <class A, class G, int K, int B0X100>
-__device__ __forceinline__ void inv_lds_passes(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
-                                               typename A::V *lds) {
+template <class A, class G, int K, int B0X100, class TwP>
+__device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds) {
   if constexpr (K >= 1) {
     __syncthreads();
     auto ld = [&](int i) { return lds[lpad(i)]; };
@@ -316,9 +336,8 @@ __device__ __forceinline__ void inv_lds_passes(const A &ar, const typename A::Tw
 
 // Whole forward transform: ld(i) reads coefficient i of the input (coalesced
 // pass-0 order), the result is written through st(i, canonical) in linear order.
-template <class A, class G, class Ld, class St>
-__device__ __forceinline__ void ntt_forward(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
-                                            typename A::V *lds, Ld ld, St st) {
+template <class A, class G, class TwP, class Ld, class St>
+__device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typename A::V *lds, Ld ld, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
   auto st_lds = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
   fwd_pass<A, G, 0>(ar, tw, tid, ld, st_lds);
@@ -333,9 +352,8 @@ __device__ __forceinline__ void ntt_forward(const A &ar, const typename A::Tw *_
 
 // Whole inverse transform of values already placed in LDS (linear order, bound
 // B0X100/100 q); pass 0 writes st(i, canonical) in coalesced order.
-template <class A, class G, int B0X100, class St>
-__device__ __forceinline__ void ntt_inverse_from_lds(const A &ar, const typename A::Tw *__restrict__ tw, int tid,
-                                                     typename A::V *lds, St st) {
+template <class A, class G, int B0X100, class TwP, class St>
+__device__ __forceinline__ void ntt_inverse_from_lds(const A &ar, TwP tw, int tid, typename A::V *lds, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
   inv_lds_passes<A, G, G::NPASS - 1, B0X100>(ar, tw, tid, lds);
   __syncthreads();

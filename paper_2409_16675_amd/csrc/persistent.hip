@@ -4,19 +4,25 @@
 // The host builds a task table: for every job, forward-transform tasks for its
 // input ciphertext planes and pack-lift-transform tasks for its plaintext
 // planes ("pre" tasks), then, after all pre tasks of all jobs, one
-// multiply-accumulate + inverse-transform task per output plane group.  A grid
-// of one 1024-thread workgroup per compute unit drains the table through an
-// atomic counter.  Each workgroup owns 16384 coefficients of LDS per task: one
-// plane at N = 16384, two at N = 8192, four at N = 4096 (every thread always
-// holds 16 coefficients, so the register budget does not depend on N).
+// multiply-accumulate + inverse-transform task per output plane group.  The
+// grid holds as many workgroups as fit on the chip at once (LDS-limited), and
+// they drain the table through atomic counters: one shared queue for the pre
+// tasks, then one queue of dependent tasks per XCD (contiguous runs of output
+// planes, so outputs sharing inputs share an L2), stolen from other XCDs once a
+// workgroup's own queue is empty.  A workgroup owns 2^SLAB coefficients of LDS
+// per task: one plane at the largest ring degree of the variant, several
+// planes of smaller degrees side by side; every thread holds 2^LOGE
+// coefficients whatever the degree, so the register budget does not depend on N.
 //
 // A multiply-accumulate task of job j waits until every pre task of job j has
 // finished (per-job counter, release/acquire at agent scope).  Because every
-// pre task precedes every multiply-accumulate task in the table, a waiting
+// pre task precedes every multiply-accumulate task in the table, and a
+// workgroup takes no dependent task before the pre queue is empty, a waiting
 // task only waits on tasks already taken by running workgroups, so the wait
 // always ends; it is also bounded by a spin limit that raises an error flag.
 #include "batch.hpp"
 #include "ntt.hpp"
+#include "mac.hpp"
 
 namespace he {
 
@@ -24,46 +30,10 @@ namespace he {
 constexpr int kWaitVmcnt0 = 0x0F70;
 
 template <class A>
-struct PTw;
-template <>
-struct PTw<ArF64> {
-  __device__ static const TwF64 *fwd(const PJob &j) { return (const TwF64 *)j.tw_fwd; }
-  __device__ static const TwF64 *inv(const PJob &j) { return (const TwF64 *)j.tw_inv; }
-};
-template <>
-struct PTw<ArU64> {
-  __device__ static const TwU64 *fwd(const PJob &j) { return (const TwU64 *)j.tw_fwd; }
-  __device__ static const TwU64 *inv(const PJob &j) { return (const TwU64 *)j.tw_inv; }
-};
-
-template <class A>
-struct PMac;
-template <>
-struct PMac<ArF64> {
-  static constexpr int kChunk = 8;
-  double acc = 0.0;
-  __device__ __forceinline__ void add(const ArF64 &ar, uint64_t a, uint64_t b) { acc += ar.mulv((double)a, (double)b); }
-  __device__ __forceinline__ void fold(const ArF64 &ar, const PrimeK &) { acc = ar.reduce(acc); }
-  __device__ __forceinline__ double value() const { return acc; }
-};
-template <>
-struct PMac<ArU64> {
-  static constexpr int kChunk = 15;
-  uint64_t lo = 0, hi = 0;
-  __device__ __forceinline__ void add(const ArU64 &, uint64_t a, uint64_t b) {
-    const uint64_t pl = a * b, ph = __umul64hi(a, b);
-    const uint64_t nl = lo + pl;
-    hi += ph + (nl < lo ? 1u : 0u);
-    lo = nl;
-  }
-  __device__ __forceinline__ void fold(const ArU64 &ar, const PrimeK &pk) {
-    uint64_t x = ar.mul(hi, pk.r64, pk.r64s) + ar.mul(lo, 1, pk.one_s);
-    x = x >= ar.two_q ? x - ar.two_q : x;
-    x = x >= ar.q ? x - ar.q : x;
-    lo = x;
-    hi = 0;
-  }
-  __device__ __forceinline__ uint64_t value() const { return lo; }
+struct PTw {
+  using T = typename A::Tw;
+  __device__ static const HE_GLOBAL T *fwd(const PJob &j) { return as_global((const T *)j.tw_fwd); }
+  __device__ static const HE_GLOBAL T *inv(const PJob &j) { return as_global((const T *)j.tw_inv); }
 };
 
 // One task on one plane group member.  G: geometry with E = 16.  `valid` is
@@ -81,8 +51,8 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   const PrimeK pk = jb.primes[i];
   const A ar(pk);
   if (tk.kind == PT_FWD_CT) {
-    const uint64_t *src = jb.ct_in + (size_t)plane * G::N;
-    uint64_t *dst = jb.ct_hat + (size_t)plane * G::N;
+    const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
+    HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
     auto ld = [&](int k) { return ar.load(valid ? src[k] : 0ull); };
     auto st = [&](int k, uint64_t v) {
       if (valid) dst[k] = v;
@@ -90,12 +60,12 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (tk.kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
-    uint64_t *dst = jb.pt_hat + (size_t)plane * G::N;
+    HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
     auto st = [&](int k, uint64_t v) {
       if (valid) dst[k] = v;
     };
     if (jb.pkind == PK_POLY) {
-      const int64_t *src = (const int64_t *)jb.plain + (size_t)pp * G::N;
+      const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
       auto ld = [&](int k) { return ar.load_signed(valid ? src[k] : 0ll); };
       ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
@@ -103,7 +73,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
 #pragma unroll
       for (int j = 0; j < G::E; ++j) lds_g[lpad(j * G::NT + tid_g)] = ar.load(0ull);
       __syncthreads();
-      const int32_t *w = (const int32_t *)jb.plain;
+      const HE_GLOBAL int32_t *w = as_global((const int32_t *)jb.plain);
       if (valid) {
         if (jb.pkind == PK_CONV) {
           const uint32_t m = pp / jb.cb, blk = pp % jb.cb, hh = jb.h * jb.h;
@@ -136,39 +106,42 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     const uint32_t comp = (plane / L) & 1, o = plane / (2 * L);
     int t0 = 0, t1 = 0;
     if (valid) {
-      t0 = jb.row[o];
-      t1 = jb.row[o + 1];
+      t0 = as_global(jb.row)[o];
+      t1 = as_global(jb.row)[o + 1];
     }
-    PMac<A> acc[G::E];
-    for (int t = t0; t < t1; t += PMac<A>::kChunk) {
-      const int te = min(t + PMac<A>::kChunk, t1);
+    const HE_GLOBAL int32_t *cti = as_global(jb.cti), *pti = as_global(jb.pti);
+    const HE_GLOBAL uint64_t *ct_hat = as_global((const uint64_t *)jb.ct_hat), *pt_hat = as_global((const uint64_t *)jb.pt_hat);
+    MacAcc<A> acc[G::E];
+    for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
+      const int te = min(t + MacAcc<A>::kChunk, t1);
       for (int tt = t; tt < te; ++tt) {
-        const uint64_t *a = jb.ct_hat + ((size_t)(jb.cti[tt] * 2 + comp) * L + i) * G::N;
-        const uint64_t *b = jb.pt_hat + ((size_t)jb.pti[tt] * L + i) * G::N;
-#pragma unroll
-        for (int j = 0; j < G::E; ++j) {
-          const int k = j * G::NT + tid_g;
-          acc[j].add(ar, a[k], b[k]);
-        }
+        const HE_GLOBAL uint64_t *a = ct_hat + ((size_t)(cti[tt] * 2 + comp) * L + i) * G::N;
+        const HE_GLOBAL uint64_t *b = pt_hat + ((size_t)pti[tt] * L + i) * G::N;
+        mac_term<A, G::E, G::NT>(ar, acc, a, b, tid_g);
       }
 #pragma unroll
       for (int j = 0; j < G::E; ++j) acc[j].fold(ar, pk);
     }
 #pragma unroll
     for (int j = 0; j < G::E; ++j) lds_g[lpad(j * G::NT + tid_g)] = acc[j].value();
-    uint64_t *dst = jb.ct_out + (size_t)plane * G::N;
+    HE_GLOBAL uint64_t *dst = as_global(jb.ct_out) + (size_t)plane * G::N;
     const uint64_t q = pk.q;
-    const bool accum = jb.accumulate != 0;
-    auto st = [&](int k, uint64_t v) {
-      if (!valid) return;
-      if (accum) {
-        const uint64_t s = dst[k] + v;
-        dst[k] = s >= q ? s - q : s;
-      } else {
-        dst[k] = v;
-      }
-    };
-    ntt_inverse_from_lds<A, G, 51>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+    // the accumulate choice is uniform over the task: one inverse transform per
+    // store kind keeps the per-coefficient stores free of branches
+    if (jb.accumulate) {
+      auto st = [&](int k, uint64_t v) {
+        if (valid) {
+          const uint64_t s = dst[k] + v;
+          dst[k] = s >= q ? s - q : s;
+        }
+      };
+      ntt_inverse_from_lds<A, G, 51>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+    } else {
+      auto st = [&](int k, uint64_t v) {
+        if (valid) dst[k] = v;
+      };
+      ntt_inverse_from_lds<A, G, 51>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+    }
   }
 }
 
@@ -182,6 +155,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
 // the producers' release) later tasks of the same job read the finished data.
 template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
 struct PCfg {
+  static_assert(LOGN_MIN - LOGE >= 6, "a plane group must hold whole waves");
   static constexpr int NT = 1 << (SLAB - LOGE);
   static constexpr int LDS_BYTES = ((1 << SLAB) + (1 << (SLAB - 5))) * 8;
   static constexpr int WG_PER_CU = (163840 / (LDS_BYTES + 512)) < 1 ? 1 : (163840 / (LDS_BYTES + 512));
@@ -191,7 +165,7 @@ struct PCfg {
 template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
 __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
                              (PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::MINW)) void k_persistent(
-    const PTask *__restrict__ tasks, uint32_t n_tasks, const PJob *__restrict__ jobs, uint32_t n_jobs,
+    const PTask *__restrict__ tasks, uint32_t n_tasks, XQ xq, const PJob *__restrict__ jobs, uint32_t n_jobs,
     uint32_t *__restrict__ ctl, uint32_t spin_limit, uint32_t strict) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_task, s_wait;
@@ -203,16 +177,34 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     for (int k = 0; k < 64; ++k) s_ready[k] = 0u;
   // (The caches are invalidated before the launch and written back after it by
   // k_edge_fence, see launch_persistent.)
-  // thread 0 keeps the index of the following task in flight while the current
-  // one runs, so the queue atomic's latency is hidden
+  // Task source: the shared queue of pre tasks [0, xq.b[0]) first; then this
+  // XCD's queue of dependent tasks (workgroups are dealt round-robin over the
+  // XCDs, so blockIdx % 8 is the XCD), then the other XCDs' queues in turn.
+  // Thread 0 keeps the following task in flight while the current one runs.
+  const uint32_t my_xcd = blockIdx.x % kXcds;
+  uint32_t q = 0;            // 0: pre queue; 1..8: dependent queue (my_xcd + q - 1) % 8
+  auto grab = [&]() -> uint32_t {
+    while (q <= (uint32_t)kXcds) {
+      if (q == 0) {
+        const uint32_t t0 = atomicAdd(head, 1u);
+        if (t0 < xq.b[0]) return t0;
+      } else {
+        const uint32_t x = (my_xcd + q - 1) % kXcds;
+        const uint32_t t0 = xq.b[x] + atomicAdd(ctl + CTL_XQ + 32 * x, 1u);
+        if (t0 < xq.b[x + 1]) return t0;
+      }
+      ++q;
+    }
+    return n_tasks;
+  };
   uint32_t next = 0;
-  if (tid == 0) next = atomicAdd(head, 1u);
+  if (tid == 0) next = grab();
   for (;;) {
     // thread 0 takes the next task and decides, for the whole workgroup, whether
     // it must wait for the job's pre tasks (so every thread takes the same branch)
     if (tid == 0) {
       const uint32_t t0 = next;
-      if (t0 < n_tasks) next = atomicAdd(head, 1u);
+      if (t0 < n_tasks) next = grab();
       uint32_t w = 0;
       if (t0 < n_tasks) {
         const PTask k0 = tasks[t0];
@@ -223,24 +215,29 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
       s_wait = w;
     }
     __syncthreads();
-    const uint32_t t = s_task;
-    const uint32_t must_wait = s_wait;
+    // the task index and the wait decision are workgroup-uniform: keep them (and
+    // the task and job fields loaded through them) in scalar registers
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_task);
+    const uint32_t must_wait = __builtin_amdgcn_readfirstlane(s_wait);
     __syncthreads();
     if (t >= n_tasks) break;
     const PTask tk = tasks[t];
     const PJob &jb = jobs[tk.job];
     if (must_wait) {
       if (tid == 0) {
-        uint32_t spins = 0;
+        // every waiting workgroup polls the same counter, so back off (up to
+        // about 1 us between polls) to keep the polls from crowding the memory
+        // channel that the producers are using
+        uint32_t spins = 0, backoff = 1;
         while (__hip_atomic_load(done + tk.job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jb.n_pre) {
-          __builtin_amdgcn_s_sleep(2);
+          for (uint32_t k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(8);
+          backoff = backoff < 6 ? backoff + 1 : 6;
           if (++spins > spin_limit) {
             atomicOr(err, 1u);
             break;
           }
         }
-        if (strict & 4u) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (tk.job < 2048) s_ready[tk.job >> 5] |= 1u << (tk.job & 31);
       }
       __syncthreads();
@@ -248,7 +245,9 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     }
     const int logn = (int)jb.logN;
     const int logt = logn - LOGE;
-    const int group = tid >> logt;
+    // a plane group has at least one whole wave (2^logt >= 64 threads), so the
+    // group index is wave-uniform
+    const int group = __builtin_amdgcn_readfirstlane(tid >> logt);
     const int tid_g = tid & ((1 << logt) - 1);
     const int words = (1 << logn) + (1 << (logn - 5));
     typename A::V *lds_g = lds + (size_t)group * words;
@@ -296,8 +295,8 @@ __global__ void k_edge_fence(int release) {
 }
 
 template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
-static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const PJob *jobs, uint32_t n_jobs, uint32_t *ctl,
-                           uint32_t grid, uint32_t spin_limit, uint32_t strict, hipStream_t st) {
+static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs, uint32_t n_jobs,
+                           uint32_t *ctl, uint32_t grid, uint32_t spin_limit, uint32_t strict, hipStream_t st) {
   using C = PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>;
   static bool set = false;
   if (!set) {
@@ -307,7 +306,7 @@ static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const PJob *job
     set = true;
   }
   hipLaunchKernelGGL((k_persistent<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>), dim3(grid), dim3(C::NT), C::LDS_BYTES, st,
-                     tasks, n_tasks, jobs, n_jobs, ctl, spin_limit, strict);
+                     tasks, n_tasks, xq, jobs, n_jobs, ctl, spin_limit, strict);
   return hipGetLastError();
 }
 
@@ -328,17 +327,16 @@ bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, PVarian
   return true;
 }
 
-hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const PJob *jobs,
+hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
                              uint32_t strict, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ctl, ctl_words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (!(strict & 8u)) {
-    hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-#define HE_P(A, S, E, MN, MX) launch_p<A, S, E, MN, MX>(tasks, n_tasks, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
+  hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+#define HE_P(A, S, E, MN, MX) \
+  launch_p<A, S, E, MN, MX>(tasks, n_tasks, xq, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
   if (v.arith == HE_ARITH_F64) {
     if (v.slab == 12 && v.loge == 5) e = HE_P(ArF64, 12, 5, 12, 12);
     else if (v.slab == 13 && v.loge == 5) e = HE_P(ArF64, 13, 5, 13, 13);
@@ -350,11 +348,8 @@ hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_t
   }
 #undef HE_P
   if (e != hipSuccess) return e;
-  if (!(strict & 8u)) {
-    hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 1);
-    e = hipGetLastError();
-  }
-  return e;
+  hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 1);
+  return hipGetLastError();
 }
 
 }  // namespace he

@@ -237,7 +237,8 @@ static void server_loop(he_server *S) {
         std::vector<PTask> tasks;
         std::vector<PJob> pjobs;
         he_batch_info info;
-        st = build_tables(refs, ws, arith, v.slab, tasks, pjobs, info);
+        XQ xq{};
+        st = build_tables(refs, ws, arith, v.slab, tasks, pjobs, info, xq.b);
         if (st == HE_OK) st = slot_reserve(sl, tasks.size(), pjobs.size());
         if (st == HE_OK) {
           std::copy(tasks.begin(), tasks.end(), sl.h_tasks);
@@ -249,8 +250,8 @@ static void server_loop(he_server *S) {
           (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->p.device);
           const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>((size_t)cus * v.wg_per_cu, tasks.size()));
           if (e == hipSuccess)
-            e = launch_persistent(v, sl.d_tasks, (uint32_t)tasks.size(), sl.d_jobs, (uint32_t)pjobs.size(), sl.d_ctl,
-                                  CTL_DONE + (uint32_t)pjobs.size(), grid, 1u << 24, 0, sl.st);
+            e = launch_persistent(v, sl.d_tasks, (uint32_t)tasks.size(), xq, sl.d_jobs, (uint32_t)pjobs.size(), sl.d_ctl,
+                                  CTL_DONE + (uint32_t)pjobs.size(), grid, kSpinLimit, 0, sl.st);
           if (e == hipSuccess) e = hipMemcpyAsync(sl.h_err, sl.d_ctl + CTL_ERR, 4, hipMemcpyDeviceToHost, sl.st);
         }
       }
