@@ -9,11 +9,14 @@ Every step transforms the 16 input ciphertexts, packs and transforms the 16
 weight polynomials, multiply-accumulates and inverse-transforms the outputs.
 
 Prints one JSON line.  `value` is the whole-job CPMul-accumulate rate of the
-default (fused / batched) path with inputs already resident in HBM; the plain
-per-layer path (separate transform, multiply-accumulate and inverse kernels)
-is reported beside it, as are transforms per second, the roofline of the
+batched path -- the persistent fused kernel replayed from a HIP graph, running
+several independent instances of the layer (each its own encrypted input batch
+and weights, all resident in HBM) per launch, exactly --steps layer steps in
+the timed region -- next to the plain per-layer path (separate transform,
+multiply-accumulate and inverse kernels) and the fused per-layer path on the
+same MI355X.  Also reported: transforms per second, the roofline of the
 dominant kernel (timed with HIP events on its launch stream during the timed
-region) and the CPU oracle timed on the host cores.
+region), serving latency, and the CPU oracle timed on the host cores.
 """
 import argparse
 import json
@@ -39,6 +42,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--jobs-per-launch", type=int, default=5,
+                    help="layer jobs (steps) the batched path runs per persistent launch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--calib-copy", action="store_true",
@@ -47,27 +52,33 @@ def parse():
     return ap.parse_args()
 
 
-def workload(he, synth, torch):
+def workload(he, synth, torch, n_layers=1):
+    """The conv layer, `n_layers` independent instances of it (input batch and
+    weights drawn from their own seeded streams), inputs encrypted on the device."""
     N, L, B, C, M, H, W, h, P = 8192, 3, 16, 3, 16, 32, 32, 3, 1
+    import numpy as np
     ctx = he.Context(N, L, prime_bits=50)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=W, h=h, P=P)
     info = plan.info
-    x = synth.int8_uniform(synth.rng(2, synth.STREAM_ACT), (B, C, H, W))
-    w = synth.int8_uniform(synth.rng(2, synth.STREAM_PT), (M, C, h, h))
-    polys = he.he_pack_input(plan.h, x.reshape(-1), B * info["cb"] * N).reshape(-1, N)
-    # encrypt on the device with the library (client side, outside the timed region)
-    import numpy as np
     s = synth.ternary(synth.rng(2, synth.STREAM_SK), N)
-    ga, ge = synth.rng(2, synth.STREAM_A), synth.rng(2, synth.STREAM_E)
-    ct_in = he.empty_u64((polys.shape[0], 2, L, N))
     ds = torch.from_numpy(s.astype(np.int8)).cuda()
-    for k in range(polys.shape[0]):
-        a = he.to_device_u64(synth.uniform_residues(ga, (), ctx.q, N))
-        e = torch.from_numpy(synth.small_error(ge, N).astype(np.int32)).cuda()
-        m = torch.from_numpy(np.remainder(polys[k], synth.T_PLAIN).astype(np.int64)).cuda()
-        he.he_encrypt(ctx.h, ds, m, a, e, ct_in[k])
-    dw = torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda()
-    return dict(ctx=ctx, plan=plan, info=info, ct_in=ct_in, w=dw, x=x, wh=w, N=N, L=L,
+    layers = []
+    for j in range(n_layers):
+        x = synth.int8_uniform(synth.rng(2, synth.STREAM_ACT, j), (B, C, H, W))
+        w = synth.int8_uniform(synth.rng(2, synth.STREAM_PT, j), (M, C, h, h))
+        polys = he.he_pack_input(plan.h, x.reshape(-1), B * info["cb"] * N).reshape(-1, N)
+        # encrypt on the device with the library (client side, outside the timed region)
+        ga, ge = synth.rng(2, synth.STREAM_A, j), synth.rng(2, synth.STREAM_E, j)
+        ct_in = he.empty_u64((polys.shape[0], 2, L, N))
+        for k in range(polys.shape[0]):
+            a = he.to_device_u64(synth.uniform_residues(ga, (), ctx.q, N))
+            e = torch.from_numpy(synth.small_error(ge, N).astype(np.int32)).cuda()
+            m = torch.from_numpy(np.remainder(polys[k], synth.T_PLAIN).astype(np.int64)).cuda()
+            he.he_encrypt(ctx.h, ds, m, a, e, ct_in[k])
+        dw = torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda()
+        layers.append(dict(ct_in=ct_in, w=dw, x=x, wh=w))
+    return dict(ctx=ctx, plan=plan, info=info, ct_in=layers[0]["ct_in"], w=layers[0]["w"], x=layers[0]["x"],
+                wh=layers[0]["wh"], layers=layers, N=N, L=L,
                 config=dict(workload="conv2d forward, batch 16 x 3x32x32 -> 16 channels, 3x3 kernel, stride 1, pad 1; "
                                      "N=8192, 3 primes of 50 bits, t=65537; 256 CPMul-accumulates per step",
                             batch=B, in_channels=C, out_channels=M, map=[H, W], kernel=h, pad=P, N=N, L=L,
@@ -100,29 +111,48 @@ def time_path(he, torch, wl, flags, steps, warmup, profile=False):
     return (t1 - t0) / steps, stats, out
 
 
-def time_batched(he, torch, wl, steps, warmup):
-    """The persistent fused kernel (one launch per step, replayed from a HIP graph)."""
+def time_batched(he, torch, wl, steps, warmup, per_launch):
+    """The persistent fused kernel, replayed from a HIP graph, `per_launch` layer
+    jobs (steps) per launch; exactly `steps` steps are timed (a last launch with
+    fewer jobs takes the remainder).  Returns seconds per step, the persistent
+    kernel's average duration per full launch, job 0's output, batch info."""
     ctx, plan = wl["ctx"], wl["plan"]
-    out = he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"]))
-    b = he.he_batch_create(0)
-    he.he_batch_add(b, ctx.h, plan.h, wl["ct_in"], wl["w"], out, 0)
-    he.he_batch_build(b, he.HE_BATCH_GRAPH)
     stream = torch.cuda.current_stream()
+
+    def make(n):
+        b = he.he_batch_create(0)
+        outs = []
+        for j in range(n):
+            lay = wl["layers"][j % len(wl["layers"])]
+            out = he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"]))
+            he.he_batch_add(b, ctx.h, plan.h, lay["ct_in"], lay["w"], out, 0)
+            outs.append(out)
+        he.he_batch_build(b, he.HE_BATCH_GRAPH)
+        return b, outs
+
+    per_launch = max(1, min(per_launch, steps))
+    full, rest = steps // per_launch, steps % per_launch
+    b, outs = make(per_launch)
+    br = make(rest) if rest else None
     for _ in range(warmup):
         he.he_batch_run(b, stream)
     he.he_batch_sync(b, stream)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(full)]
     t0 = time.perf_counter()
     for a, z in ev:
         a.record(stream)
         he.he_batch_run(b, stream)
         z.record(stream)
+    if br:
+        he.he_batch_run(br[0], stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     he.he_batch_sync(b, stream)
     kern_ms = [a.elapsed_time(z) for a, z in ev]
     info = he.he_batch_get_info(b)
-    return (t1 - t0) / steps, sum(kern_ms) / len(kern_ms), out, b, info
+    if br:
+        he.he_batch_destroy(br[0])
+    return (t1 - t0) / steps, (sum(kern_ms) / len(kern_ms) if kern_ms else float("nan")), outs, b, info
 
 
 def ntt_rate(he, torch, wl, iters=20):
@@ -160,21 +190,23 @@ def roofline(wl, stats):
 
 
 def roofline_persistent(wl, kern_ms, binfo):
-    """Roofline of the persistent kernel, which runs the whole step: forward transforms of
-    inputs and packed plaintexts, multiply-accumulate, inverse transforms."""
+    """Roofline of the persistent kernel, which runs whole steps: forward transforms of
+    inputs and packed plaintexts, multiply-accumulate, inverse transforms, for every
+    job of the launch."""
     info, N, L = wl["info"], wl["N"], wl["L"]
+    nj = binfo["n_jobs"]
     logn = N.bit_length() - 1
     avg_s = kern_ms / 1e3
     bfly = (N // 2) * logn
     ops = (binfo["fwd_planes"] * bfly * OPS_BFLY
            + binfo["inv_planes"] * (bfly * OPS_BFLY + (N // 2) * OPS_MODMUL)
-           + info["n_terms"] * 2 * L * N * OPS_MAC_TERM)
-    bytes_ = 8 * N * (info["n_ct_in"] * 2 * L + info["n_ct_out"] * 2 * L) + 4 * 16 * 3 * 9
+           + nj * info["n_terms"] * 2 * L * N * OPS_MAC_TERM)
+    bytes_ = nj * (8 * N * (info["n_ct_in"] * 2 * L + info["n_ct_out"] * 2 * L) + 4 * 16 * 3 * 9)
     alu = ops / avg_s / 1e12
     hbm = bytes_ / avg_s / 1e9
     return {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "T VALU-op/s",
             "frac": round(alu / PEAK_VALU_TOPS, 4), "traffic": None,
-            "kernel": "k_persistent (whole step: transforms, packing, MAC, inverse transforms)",
+            "kernel": "k_persistent (%d whole steps per launch: transforms, packing, MAC, inverse transforms)" % nj,
             "kernel_avg_us": round(avg_s * 1e6, 2), "ops_per_launch": int(ops), "alg_bytes_per_launch": int(bytes_),
             "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
 
@@ -268,21 +300,31 @@ def main():
         return 2
     import torch
     from paper_2409_16675_amd import he, synth
-    wl = workload(he, synth, torch)
+    wl = workload(he, synth, torch, n_layers=args.jobs_per_launch)
     n_cpmul = wl["info"]["n_terms"]
     tune = he.he_autotune(wl["ctx"].h, 512)      # set-up: picks the fastest bit-exact schedules
     chosen = {name: he.he_ctx_get_schedule(wl["ctx"].h, op) for name, op in
               (("fwd", he.HE_OP_FWD), ("inv", he.HE_OP_INV), ("mac", he.HE_OP_MAC))}
     plain_dt, _, out_plain = time_path(he, torch, wl, he.HE_UNFUSED, max(5, args.steps // 2), args.warmup)
     fused_dt, stats, out_fused = time_path(he, torch, wl, 0, max(5, args.steps // 2), args.warmup, profile=True)
-    dt, kern_ms, out, batch, binfo = time_batched(he, torch, wl, args.steps, args.warmup)
-    same = bool(torch.equal(out.view(torch.int64), out_plain.view(torch.int64)) and
+    dt, kern_ms, outs, batch, binfo = time_batched(he, torch, wl, args.steps, args.warmup, args.jobs_per_launch)
+    same = bool(torch.equal(outs[0].view(torch.int64), out_plain.view(torch.int64)) and
                 torch.equal(out_fused.view(torch.int64), out_plain.view(torch.int64)))
+    # every other job of the launch against the fused per-layer path on its own layer
+    ws = he.workspace(wl["plan"].workspace_size(0))
+    ref = he.empty_u64(tuple(outs[0].shape))
+    for j in range(1, len(outs)):
+        lay = wl["layers"][j]
+        he.he_corr_conv2d(wl["ctx"].h, wl["plan"].h, lay["ct_in"], lay["w"], ref, 0, ws, ws.numel(),
+                          torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(outs[j].view(torch.int64), ref.view(torch.int64)))
     res = {
         "metric": METRIC, "value": round(n_cpmul / dt, 1), "unit": "CPMul-acc/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
-        "path": "batched (persistent fused kernel, graph replay)",
+        "path": "batched (persistent fused kernel, graph replay, %d layer jobs per launch)" % args.jobs_per_launch,
+        "jobs_per_launch": args.jobs_per_launch,
         "plain_value": round(n_cpmul / plain_dt, 1), "plain_ms_per_step": round(plain_dt * 1e3, 4),
         "fused_value": round(n_cpmul / fused_dt, 1), "fused_ms_per_step": round(fused_dt * 1e3, 4),
         "batched_equals_fused_equals_plain": same,

@@ -60,9 +60,10 @@ struct ArF64 {
 
   __device__ __forceinline__ explicit ArF64(const PrimeK &p) : q(p.qd), qinv(p.qinv) {}
 
-  // x < 2^53: two 32-bit conversions and one FMA (exact)
+  // x < 2^52: the bits of x under the exponent of 2^52 are the double 2^52 + x
+  // (exact), so one OR and one subtraction convert it
   __device__ __forceinline__ V load(uint64_t x) const {
-    return __builtin_fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+    return __builtin_bit_cast(double, x | 0x4330000000000000ull) - 4503599627370496.0;
   }
   __device__ __forceinline__ V load_signed(int64_t x) const {
     // |x| < 2^53 here (plaintext integers); reduce into (-q, q)
@@ -70,13 +71,12 @@ struct ArF64 {
     return __builtin_fma(-__builtin_rint(d * qinv), q, d);
   }
   __device__ __forceinline__ V reduce(V x) const { return __builtin_fma(-__builtin_rint(x * qinv), q, x); }
-  // canonical residue of x, split exactly into 32-bit halves (0 <= r < 2^50)
+  // canonical residue of x as an integer: 0 <= r < q < 2^52, so 2^52 + r is
+  // exact and its mantissa bits are r
   __device__ __forceinline__ uint64_t store(V x) const {
     double r = reduce(x);          // |r| <= q/2 + 2
     r = r < 0.0 ? r + q : r;
-    const uint32_t hi = (uint32_t)(r * 2.3283064365386963e-10);   // exact scaling by 2^-32, truncation
-    const uint32_t lo = (uint32_t)__builtin_fma(-(double)hi, 4294967296.0, r);
-    return ((uint64_t)hi << 32) | lo;
+    return __builtin_bit_cast(uint64_t, r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
   }
   __device__ __forceinline__ V mul(V y, double w, double wq) const {
     double h = y * w;

@@ -182,7 +182,9 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   }
   if (b->jobs.empty()) min_logn = max_logn;
   b->arith = all_f64 ? HE_ARITH_F64 : HE_ARITH_U64;
-  persistent_variant(b->arith, min_logn, max_logn, b->var);
+  // the first job's autotuned multiply-accumulate schedule picks the thread count
+  const int pref = (!b->jobs.empty() && b->jobs[0].ctx->s_mac.arith == b->arith) ? b->jobs[0].ctx->s_mac.loge : 5;
+  persistent_variant(b->arith, min_logn, max_logn, pref, b->var);
   const uint32_t slab_n = 1u << b->var.slab;
   // workspace: transformed inputs and plaintexts per job
   const size_t nj = b->jobs.size();

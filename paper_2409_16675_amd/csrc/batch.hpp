@@ -59,7 +59,7 @@ struct PVariant {
   int arith, slab, loge, logn_min, logn_max;
   int threads = 0, lds_bytes = 0, wg_per_cu = 1;
 };
-bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, PVariant &v);
+bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pref_loge, PVariant &v);
 struct XQ {
   uint32_t b[kXcds + 1];   // queue bounds in the task table
 };

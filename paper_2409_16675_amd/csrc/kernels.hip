@@ -71,10 +71,7 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   uint64_t *dst = out + (size_t)plane * G::N;
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < G::E; ++j) {
-    const int k = j * G::NT + tid;
-    lds[lpad(k)] = ar.load(src[k]);
-  }
+  for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = ar.load(src[j * G::NT + tid]);
   auto st = [&](int k, uint64_t v) { dst[k] = v; };
   ntt_inverse_from_lds<A, G, 100>(ar, tw + (size_t)i * G::N, tid, lds, st);
 }
@@ -134,7 +131,7 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
     for (int j = 0; j < G::E; ++j) acc[j].fold(ar, *pk);
   }
 #pragma unroll
-  for (int j = 0; j < G::E; ++j) lds[lpad(j * G::NT + tid)] = acc[j].value();
+  for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = acc[j].value();
   uint64_t *dst = out + (size_t)plane * G::N;
   const uint64_t q = pk->q;
   if constexpr (ACC) {

@@ -56,8 +56,10 @@ __device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, 
     uint64_t va[B], vb[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      va[j] = a[(j0 + j) * NT + tid];
-      vb[j] = b[(j0 + j) * NT + tid];
+      // unsigned 32-bit offsets: a scalar base plus a lane offset, no 64-bit adds
+      const uint32_t k = (uint32_t)((j0 + j) * NT) + (uint32_t)tid;
+      va[j] = a[k];
+      vb[j] = b[k];
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[j0 + j].add(ar, va[j], vb[j]);

@@ -32,6 +32,13 @@ struct Geo {
 };
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lpad_c(int i) { return i + (i >> 5); }
+// LDS word of linear index j * NT + tid (tid < NT, NT a multiple of 32): the
+// two parts have disjoint bits, so the padding splits (see pass_index).
+template <class G>
+__device__ __forceinline__ int lin_lds(int tid, int j) {
+  return lpad(tid) + lpad_c(j * G::NT);
+}
 
 // Pointers read from memory (job tables) are generic; qualifying them as global
 // lets the compiler use global (not flat) loads and stores, which do not tie the
@@ -68,13 +75,20 @@ struct MinWaves {
 
 // Index of register slot (g, p) of thread tid in a pass starting at stage S0 with R stages.
 template <int LOGN, int LOGT, int S0, int R>
-__device__ __forceinline__ int pass_index(int tid, int g, int p) {
+__host__ __device__ constexpr int pass_index(int tid, int g, int p) {
   constexpr int NLOW = LOGN - S0 - R;
   const int f = (g << LOGT) | tid;
   const int low = f & ((1 << NLOW) - 1);
   const int high = f >> NLOW;
   return (high << (LOGN - S0)) | (p << NLOW) | low;
 }
+// pass_index only moves bits, so it splits into a per-thread part and a
+// compile-time part with disjoint bits:
+//   pass_index(tid, g, p) = pass_index(tid, 0, 0) + pass_index(0, g, p),
+// and so does the LDS padding, lpad(a + b) = lpad(a) + lpad(b) for disjoint
+// a and b (a shift distributes over a disjoint union of bits).  Loads and
+// stores therefore take (t, c) = (thread part, constant part); an LDS address
+// is a per-thread base plus an immediate offset.
 
 // ---------------------------------------------------------------- bound bookkeeping
 // For the lazily reduced fp64 policy: worst-case |value| / q through a pass,
@@ -226,55 +240,82 @@ __device__ __forceinline__ typename A::V reduce_gs_in(const A &ar, typename A::V
 }
 
 // ------------------------------------------------------------------------ passes
-// Forward pass K.  `ld(i)` yields the value at plane index i, `st(i, v)` stores it.
+// Twiddle slot of stage u (of R) in a pass: the thread needs the 2^u entries
+// (1 << (S0 + u)) + (high << u) + j, j < 2^u, kept in slot (1 << u) - 1 + j.
+// All of a pass's twiddles are loaded before its data, so that their latency
+// overlaps the data loads (and, in LDS passes, the barrier).
+template <class A, class G, int S0, int R, class TwP>
+__device__ __forceinline__ void load_pass_tw(TwP tw, int tid, typename A::Tw (&twr)[G::E >> R][(1 << R) - 1]) {
+  constexpr int NLOW = G::LOGN - S0 - R, NG = G::E >> R;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int high = ((g << G::LOGT) | tid) >> NLOW;
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int j = 0; j < (1 << u); ++j) twr[g][(1 << u) - 1 + j] = load_tw(tw, (1 << (S0 + u)) + ((high << u) | j));
+  }
+}
+
+// Forward pass K.  ld(t, c) yields the value at plane index t + c, st(t, c, v)
+// stores it (t: thread part, c: compile-time part, see pass_index).
 template <class A, class G, int K, class TwP, class Ld, class St>
 __device__ __forceinline__ void fwd_pass(const A &ar, TwP tw, int tid, Ld ld, St st) {
   using V = typename A::V;
-  constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
+  constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
   constexpr PassPlan pp = plan_ct<A>(R, fwd_bound_in<A, G>(K));
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
+  const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
+  typename A::Tw twr[NG][(1 << R) - 1];
+  load_pass_tw<A, G, S0, R>(tw, tid, twr);
   V v[G::E];
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
-    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p));
+    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p));
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     if ((pp.mask >> u) & 1u) {
 #pragma unroll
       for (int e = 0; e < G::E; ++e) v[e] = ar.reduce(v[e]);
     }
-    const int s = S0 + u;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      const int high = ((g << G::LOGT) | tid) >> NLOW;
 #pragma unroll
       for (int p = 0; p < (1 << R); ++p) {
         if (p & (1 << (R - 1 - u))) continue;
         const int p2 = p | (1 << (R - 1 - u));
-        const typename A::Tw w = load_tw(tw, (1 << s) + ((high << u) | (p >> (R - u))));
-        ar.ct(v[(g << R) | p], v[(g << R) | p2], w);
+        ar.ct(v[(g << R) | p], v[(g << R) | p2], twr[g][(1 << u) - 1 + (p >> (R - u))]);
       }
     }
   }
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
-    for (int p = 0; p < (1 << R); ++p) st(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p), v[(g << R) | p]);
+    for (int p = 0; p < (1 << R); ++p) st(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p), v[(g << R) | p]);
 }
 
 // Inverse pass K (stages S0+R-1 down to S0).  B0 is the bound of the transform's input.
 template <class A, class G, int K, int B0X100, class TwP, class Ld, class St>
 __device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St st) {
   using V = typename A::V;
-  constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R, NG = G::E >> R;
+  constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
   constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
+  const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
+  typename A::Tw twr[NG][(1 << R) - 1];
+  load_pass_tw<A, G, S0, R>(tw, tid, twr);
+  // stage 0 folds N^-1 in: entries 0 and 1 of the inverse table
+  typename A::Tw tn0, tn1;
+  if constexpr (S0 == 0) {
+    tn0 = load_tw(tw, 0);
+    tn1 = load_tw(tw, 1);
+  }
   V v[G::E];
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
-    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p));
+    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p));
 #pragma unroll
   for (int uu = 0; uu < R; ++uu) {
     const int u = R - 1 - uu;   // stage S0 + u, processed from the highest down
@@ -284,16 +325,14 @@ __device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St
     const int s = S0 + u;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      const int high = ((g << G::LOGT) | tid) >> NLOW;
 #pragma unroll
       for (int p = 0; p < (1 << R); ++p) {
         if (p & (1 << (R - 1 - u))) continue;
         const int p2 = p | (1 << (R - 1 - u));
         if (s == 0) {
-          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], load_tw(tw, 0), load_tw(tw, 1));
+          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], tn0, tn1);
         } else {
-          const typename A::Tw w = load_tw(tw, (1 << s) + ((high << u) | (p >> (R - u))));
-          gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], w);
+          gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], twr[g][(1 << u) - 1 + (p >> (R - u))]);
         }
       }
     }
@@ -304,20 +343,30 @@ __device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
-    for (int p = 0; p < (1 << R); ++p) st(pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, p), v[(g << R) | p]);
+    for (int p = 0; p < (1 << R); ++p) st(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p), v[(g << R) | p]);
 }
 
 // A pass loads and stores the same thread-private set of indices, so passes
 // sharing LDS need only one barrier between them.
+
+// LDS access through the split index: per-thread base lpad(t), constant lpad(c).
+template <class V>
+struct LdsAt {
+  V *lds;
+  __device__ __forceinline__ V operator()(int t, int c) const { return lds[lpad(t) + lpad_c(c)]; }
+};
+template <class V>
+struct LdsPut {
+  V *lds;
+  __device__ __forceinline__ void operator()(int t, int c, V v) const { lds[lpad(t) + lpad_c(c)] = v; }
+};
 
 // Forward passes K..NPASS-1, LDS to LDS.
 template <class A, class G, int K, class TwP>
 __device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds) {
   if constexpr (K < G::NPASS) {
     __syncthreads();
-    auto ld = [&](int i) { return lds[lpad(i)]; };
-    auto st = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
-    fwd_pass<A, G, K>(ar, tw, tid, ld, st);
+    fwd_pass<A, G, K>(ar, tw, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds});
     fwd_lds_passes<A, G, K + 1>(ar, tw, tid, lds);
   }
 }
@@ -327,27 +376,27 @@ template <class A, class G, int K, int B0X100, class TwP>
 __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds) {
   if constexpr (K >= 1) {
     __syncthreads();
-    auto ld = [&](int i) { return lds[lpad(i)]; };
-    auto st = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
-    inv_pass<A, G, K, B0X100>(ar, tw, tid, ld, st);
+    inv_pass<A, G, K, B0X100>(ar, tw, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds});
     inv_lds_passes<A, G, K - 1, B0X100>(ar, tw, tid, lds);
   }
 }
 
-// Whole forward transform: ld(i) reads coefficient i of the input (coalesced
-// pass-0 order), the result is written through st(i, canonical) in linear order.
-template <class A, class G, class TwP, class Ld, class St>
-__device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typename A::V *lds, Ld ld, St st) {
+// Whole forward transform: ld2(t, c) reads coefficient t + c of the input
+// (coalesced pass-0 order), the result is written through st(i, canonical) in
+// linear order.
+template <class A, class G, class TwP, class Ld2, class St>
+__device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typename A::V *lds, Ld2 ld2, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
-  auto st_lds = [&](int i, typename A::V v) { lds[lpad(i)] = v; };
-  fwd_pass<A, G, 0>(ar, tw, tid, ld, st_lds);
+  fwd_pass<A, G, 0>(ar, tw, tid, ld2, LdsPut<typename A::V>{lds});
   fwd_lds_passes<A, G, 1>(ar, tw, tid, lds);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < G::E; ++j) {
-    const int i = j * G::NT + tid;
-    st(i, ar.store(lds[lpad(i)]));
-  }
+  for (int j = 0; j < G::E; ++j) st(j * G::NT + tid, ar.store(lds[lin_lds<G>(tid, j)]));
+}
+// The same with ld(i) reading coefficient i.
+template <class A, class G, class TwP, class Ld, class St>
+__device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typename A::V *lds, Ld ld, St st) {
+  ntt_forward_tc<A, G>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
 }
 
 // Whole inverse transform of values already placed in LDS (linear order, bound
@@ -357,9 +406,8 @@ __device__ __forceinline__ void ntt_inverse_from_lds(const A &ar, TwP tw, int ti
   static_assert(G::NPASS >= 2, "at least two passes");
   inv_lds_passes<A, G, G::NPASS - 1, B0X100>(ar, tw, tid, lds);
   __syncthreads();
-  auto ld = [&](int i) { return lds[lpad(i)]; };
-  auto st_out = [&](int i, typename A::V v) { st(i, ar.store(v)); };
-  inv_pass<A, G, 0, B0X100>(ar, tw, tid, ld, st_out);
+  auto st_out = [&](int t, int c, typename A::V v) { st(t + c, ar.store(v)); };
+  inv_pass<A, G, 0, B0X100>(ar, tw, tid, LdsAt<typename A::V>{lds}, st_out);
 }
 
 }  // namespace he

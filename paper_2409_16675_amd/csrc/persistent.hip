@@ -71,7 +71,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
 #pragma unroll
-      for (int j = 0; j < G::E; ++j) lds_g[lpad(j * G::NT + tid_g)] = ar.load(0ull);
+      for (int j = 0; j < G::E; ++j) lds_g[lin_lds<G>(tid_g, j)] = ar.load(0ull);
       __syncthreads();
       const HE_GLOBAL int32_t *w = as_global((const int32_t *)jb.plain);
       if (valid) {
@@ -99,8 +99,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
         }
       }
       __syncthreads();
-      auto ld = [&](int k) { return lds_g[lpad(k)]; };
-      ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+      ntt_forward_tc<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, LdsAt<typename A::V>{lds_g}, st);
     }
   } else {   // PT_MAC_INV: output plane (o, comp, i)
     const uint32_t comp = (plane / L) & 1, o = plane / (2 * L);
@@ -123,7 +122,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       for (int j = 0; j < G::E; ++j) acc[j].fold(ar, pk);
     }
 #pragma unroll
-    for (int j = 0; j < G::E; ++j) lds_g[lpad(j * G::NT + tid_g)] = acc[j].value();
+    for (int j = 0; j < G::E; ++j) lds_g[lin_lds<G>(tid_g, j)] = acc[j].value();
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_out) + (size_t)plane * G::N;
     const uint64_t q = pk.q;
     // the accumulate choice is uniform over the task: one inverse transform per
@@ -310,11 +309,15 @@ static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const XQ &xq, c
   return hipGetLastError();
 }
 
-// Variants compiled: F64 single-degree 4096/8192/16384 with 32 coefficients per
-// thread, and mixed-degree variants (16 per thread) for both arithmetics.
-bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, PVariant &v) {
+// Variants compiled: F64 single-degree 4096/8192/16384 with 8, 16 or 32
+// coefficients per thread (the preferred count, normally the autotuned
+// multiply-accumulate schedule, where compiled; a workgroup has at most 1024
+// threads), and mixed-degree variants (16 per thread) for both arithmetics.
+bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pref_loge, PVariant &v) {
   if (arith == HE_ARITH_F64 && logn_min == logn_max && logn_min >= 12 && logn_min <= 14) {
-    v = PVariant{arith, (int)logn_min, 5, (int)logn_min, (int)logn_min};
+    int loge = pref_loge < 3 ? 3 : (pref_loge > 5 ? 5 : pref_loge);
+    if ((int)logn_min - loge > 10) loge = (int)logn_min - 10;
+    v = PVariant{arith, (int)logn_min, loge, (int)logn_min, (int)logn_min};
   } else if (logn_max <= 13) {
     v = PVariant{arith, 13, 4, 10, 13};
   } else {
@@ -338,9 +341,14 @@ hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_t
 #define HE_P(A, S, E, MN, MX) \
   launch_p<A, S, E, MN, MX>(tasks, n_tasks, xq, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
   if (v.arith == HE_ARITH_F64) {
-    if (v.slab == 12 && v.loge == 5) e = HE_P(ArF64, 12, 5, 12, 12);
-    else if (v.slab == 13 && v.loge == 5) e = HE_P(ArF64, 13, 5, 13, 13);
-    else if (v.slab == 14 && v.loge == 5) e = HE_P(ArF64, 14, 5, 14, 14);
+    if (v.slab == 12 && v.logn_min == 12 && v.loge == 3) e = HE_P(ArF64, 12, 3, 12, 12);
+    else if (v.slab == 12 && v.logn_min == 12 && v.loge == 4) e = HE_P(ArF64, 12, 4, 12, 12);
+    else if (v.slab == 12 && v.logn_min == 12) e = HE_P(ArF64, 12, 5, 12, 12);
+    else if (v.slab == 13 && v.logn_min == 13 && v.loge == 3) e = HE_P(ArF64, 13, 3, 13, 13);
+    else if (v.slab == 13 && v.logn_min == 13 && v.loge == 4) e = HE_P(ArF64, 13, 4, 13, 13);
+    else if (v.slab == 13 && v.logn_min == 13) e = HE_P(ArF64, 13, 5, 13, 13);
+    else if (v.slab == 14 && v.logn_min == 14 && v.loge == 4) e = HE_P(ArF64, 14, 4, 14, 14);
+    else if (v.slab == 14 && v.logn_min == 14) e = HE_P(ArF64, 14, 5, 14, 14);
     else if (v.slab == 13) e = HE_P(ArF64, 13, 4, 10, 13);
     else e = HE_P(ArF64, 14, 4, 10, 14);
   } else {

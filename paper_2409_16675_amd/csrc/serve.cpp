@@ -233,7 +233,8 @@ static void server_loop(he_server *S) {
         }
         const int arith = all_f64 ? HE_ARITH_F64 : HE_ARITH_U64;
         PVariant v{};
-        persistent_variant(arith, mn, mx, v);
+        const Ctx *c0 = take[0]->ref.ctx;
+        persistent_variant(arith, mn, mx, c0->s_mac.arith == arith ? c0->s_mac.loge : 5, v);
         std::vector<PTask> tasks;
         std::vector<PJob> pjobs;
         he_batch_info info;

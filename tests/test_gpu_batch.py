@@ -150,3 +150,35 @@ def test_batched_conv_workload_and_transformed_inputs(gpu_lib, ctxs):
     assert_equal_u64(he.to_numpy_u64(out), expect, "batched conv")
     assert_equal_u64(he.to_numpy_u64(out2), expect, "batched conv, transformed inputs")
     he.he_batch_destroy(b)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("loge", [3, 4, 5])
+def test_single_degree_variants(gpu_lib, ctxs, loge):
+    # a batch of one ring degree runs the single-degree persistent variant with the
+    # coefficients-per-thread of the context's multiply-accumulate schedule: every
+    # compiled count (8, 16, 32; the largest ring starts at 16) against the oracle,
+    # with a layer job and a multi-ciphertext FC job per ring
+    he = gpu_lib
+    for ring, (N, L) in enumerate(synth.MIX_RINGS):
+        ctx = ctxs[(N, L)]
+        if (he.HE_ARITH_F64, loge) not in he.compiled_schedules(N):
+            continue                       # more than 1024 threads per plane
+        saved = he.he_ctx_get_schedule(ctx.h, he.HE_OP_MAC)
+        he.he_ctx_set_schedule(ctx.h, he.HE_OP_MAC, he.HE_ARITH_F64, loge)
+        try:
+            jobs = [make_job(he, ctxs, lay, ring, 300 + 10 * loge + k) for k, lay in enumerate([0, 4])]
+            expect = [oracle_out(j) for j in jobs]
+            b = he.he_batch_create(0)
+            for j in jobs:
+                he.he_batch_add(b, j["ctx"].h, j["plan"].h, j["d_ct"], j["d_w"], j["out"], 0)
+            he.he_batch_build(b, he.HE_BATCH_GRAPH)
+            print("case variant N=%d loge=%d" % (N, loge), flush=True)
+            for rep in range(2):
+                he.he_batch_run(b)
+                he.he_batch_sync(b)
+                for k, j in enumerate(jobs):
+                    assert_equal_u64(he.to_numpy_u64(j["out"]), expect[k], "N=%d loge=%d job %d rep %d" % (N, loge, k, rep))
+            he.he_batch_destroy(b)
+        finally:
+            he.he_ctx_set_schedule(ctx.h, he.HE_OP_MAC, *saved)
