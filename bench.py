@@ -211,10 +211,11 @@ def roofline_persistent(wl, kern_ms, binfo):
             "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
 
 
-def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4):
+def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4, sweep=(20000.0, 100000.0)):
     """Poisson arrivals (mean `rate` jobs/s) drawn from the uneven layer mix, sessions of 6
     jobs whose transformed inputs stay resident, 64 GB admission cap; continuous batching
-    against the sequential per-layer server on the same trace."""
+    against the sequential per-layer server on the same trace; then the same at the
+    higher arrival rates of `sweep` (where the sequential server saturates)."""
     import numpy as np
     ctxs = {(N, L): he.Context(N, L) for N, L in synth.MIX_RINGS}
     kinds = {}
@@ -236,8 +237,6 @@ def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4):
             kinds[(li, ri)] = dict(ctx=ctx, plan=plan, w=torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda(),
                                    bufs=bufs, cpmul=info["n_terms"])
     mix = synth.job_mix(n_jobs, workload=5)
-    arr = synth.poisson_arrivals(n_jobs, rate)
-    arr = arr - arr[0]
     jobs, ctx_list, cpmul = [], [], 0
     for k, (li, ri) in enumerate(mix):
         kd = kinds[(li, ri)]
@@ -246,28 +245,38 @@ def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4):
         ctx_list.append(kd["ctx"].h)
         cpmul += kd["cpmul"]
     sessions = np.arange(n_jobs, dtype=np.uint64) // 6 + 1
+
+    def run(r):
+        arr = synth.poisson_arrivals(n_jobs, r)
+        arr = arr - arr[0]
+        out = {}
+        for name, mode in (("continuous", he.HE_SERVE_CONTINUOUS), ("sequential", he.HE_SERVE_SEQUENTIAL)):
+            srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
+                                      max_batch_jobs=64, session_jobs=6)
+            # warm the kernels and the arena with a short burst
+            he.he_server_replay(srv, ctx_list[:32], jobs[:32], np.zeros(32))
+            he.he_server_destroy(srv)
+            srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
+                                      max_batch_jobs=64, session_jobs=6)
+            t0 = time.perf_counter()
+            lat = he.he_server_replay(srv, ctx_list, jobs, arr, sessions, he.HE_SERVE_KEEP_RESIDENT)
+            wall = time.perf_counter() - t0
+            st = he.he_server_stats(srv)
+            he.he_server_destroy(srv)
+            out[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                         "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                         "throughput_jobs_per_s": round(n_jobs / st["span_s"], 1),
+                         "cpmul_per_s": round(cpmul / st["span_s"], 1),
+                         "epochs": st["epochs"], "single_job_epochs": st["single_epochs"],
+                         "mean_jobs_per_epoch": round(st["mean_jobs_per_epoch"], 2),
+                         "peak_footprint_GB": round(st["peak_bytes"] / 2 ** 30, 3), "wall_s": round(wall, 3)}
+        return out
+
     res = {"rate_jobs_per_s": rate, "jobs": n_jobs, "mix": "uneven 5-layer x 3-ring mix, batch 1",
            "session_jobs": 6, "cap_GB": 64}
-    for name, mode in (("continuous", he.HE_SERVE_CONTINUOUS), ("sequential", he.HE_SERVE_SEQUENTIAL)):
-        srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
-                                  max_batch_jobs=64, session_jobs=6)
-        # warm the kernels and the arena with a short burst
-        he.he_server_replay(srv, ctx_list[:32], jobs[:32], np.zeros(32))
-        he.he_server_destroy(srv)
-        srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
-                                  max_batch_jobs=64, session_jobs=6)
-        t0 = time.perf_counter()
-        lat = he.he_server_replay(srv, ctx_list, jobs, arr, sessions, he.HE_SERVE_KEEP_RESIDENT)
-        wall = time.perf_counter() - t0
-        st = he.he_server_stats(srv)
-        he.he_server_destroy(srv)
-        res[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                     "mean_ms": round(float(lat.mean()) * 1e3, 3),
-                     "throughput_jobs_per_s": round(n_jobs / st["span_s"], 1),
-                     "cpmul_per_s": round(cpmul / st["span_s"], 1),
-                     "epochs": st["epochs"], "mean_jobs_per_epoch": round(st["mean_jobs_per_epoch"], 2),
-                     "peak_footprint_GB": round(st["peak_bytes"] / 2 ** 30, 3), "wall_s": round(wall, 3)}
+    res.update(run(rate))
+    res["sweep"] = [dict(rate_jobs_per_s=r, **run(r)) for r in sweep]
     return res
 
 

@@ -309,6 +309,7 @@ typedef struct {
   double p50_s, p99_s, mean_s, max_s;
   double span_s;              /* first arrival to last completion */
   uint64_t peak_bytes, in_use_bytes;
+  uint64_t single_epochs;     /* continuous mode: epochs of one job, run by the per-layer kernels */
 } he_server_info;
 
 /* Start a server (device arena, stream slots and the server thread). */

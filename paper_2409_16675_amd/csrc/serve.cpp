@@ -103,7 +103,7 @@ struct he_server {
   bool stop = false;
   uint64_t next_ticket = 1;
   size_t in_use = 0, peak_in_use = 0;
-  uint64_t epochs = 0, epoch_jobs = 0, rejected = 0;
+  uint64_t epochs = 0, epoch_jobs = 0, rejected = 0, single_epochs = 0;
   std::vector<double> lat;
   double first_arrive = 0, last_done = 0;
   he_status thread_error = HE_OK;
@@ -219,6 +219,14 @@ static void server_loop(he_server *S) {
         SJob *j = take[0];
         st = run_layer(*j->ref.ctx, *j->ref.plan, j->ref.job.ct_in, j->ref.job.plain, j->ref.job.ct_out,
                        j->ref.job.flags | HE_UNFUSED, S->arena.base + j->ws_off, j->ws_bytes, sl.st);
+      } else if (take.size() == 1) {
+        // a lone job: the fused per-layer kernels have less fixed cost than a
+        // persistent launch (no dependency waits, no cache-maintenance kernels)
+        SJob *j = take[0];
+        *sl.h_err = 0u;
+        st = run_layer(*j->ref.ctx, *j->ref.plan, j->ref.job.ct_in, j->ref.job.plain, j->ref.job.ct_out,
+                       j->ref.job.flags & ~HE_UNFUSED, S->arena.base + j->ws_off, j->ws_bytes, sl.st);
+        S->single_epochs++;
       } else {
         std::vector<JobRef> refs;
         std::vector<char *> ws;
@@ -346,8 +354,11 @@ static he_status submit_at(he_server *S, he_ctx *ctx, const he_job *job, uint64_
   j->ref = JobRef{ctx->c, &job->plan->p, *job};
   j->session = session;
   j->keep = session != 0 && (flags & HE_SERVE_KEEP_RESIDENT);
-  j->ws_bytes = S->p.mode == HE_SERVE_SEQUENTIAL ? layer_ws_bytes(*ctx->c, job->plan->p, job->flags | HE_UNFUSED)
-                                                 : job_ws_bytes(j->ref);
+  // continuous mode runs a job alone in an epoch through the fused per-layer
+  // path and with others through the batch kernel: room for either
+  j->ws_bytes = S->p.mode == HE_SERVE_SEQUENTIAL
+                    ? layer_ws_bytes(*ctx->c, job->plan->p, job->flags | HE_UNFUSED)
+                    : std::max(job_ws_bytes(j->ref), layer_ws_bytes(*ctx->c, job->plan->p, job->flags & ~HE_UNFUSED));
   j->footprint = al4k(j->ws_bytes) + job_buffers_bytes(j->ref);
   std::lock_guard<std::mutex> g(S->mu);
   if (j->footprint > S->p.mem_cap_bytes || j->ws_bytes > S->arena.size) {
@@ -395,6 +406,7 @@ he_status he_server_stats(he_server *S, he_server_info *out) {
   out->completed = l.size();
   out->rejected = S->rejected;
   out->epochs = S->epochs;
+  out->single_epochs = S->single_epochs;
   out->mean_jobs_per_epoch = S->epochs ? (double)S->epoch_jobs / S->epochs : 0.0;
   out->p50_s = pct(0.50);
   out->p99_s = pct(0.99);

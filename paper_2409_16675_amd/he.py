@@ -383,7 +383,7 @@ class he_server_info(ctypes.Structure):
     _fields_ = [("completed", c_u64), ("rejected", c_u64), ("epochs", c_u64), ("mean_jobs_per_epoch", ctypes.c_double),
                 ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
                 ("max_s", ctypes.c_double), ("span_s", ctypes.c_double), ("peak_bytes", c_u64),
-                ("in_use_bytes", c_u64)]
+                ("in_use_bytes", c_u64), ("single_epochs", c_u64)]
 
 
 def he_server_create(mem_cap_bytes=64 << 30, mode=HE_SERVE_CONTINUOUS, device=0, arena_bytes=0, max_batch_jobs=0,

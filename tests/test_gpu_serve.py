@@ -70,8 +70,9 @@ def test_admission_cap_queues_and_refuses(gpu_lib, ctxs):
     he = gpu_lib
     j_small = make_job(he, ctxs, 3, 0, 700)     # FC 256->10 at N=4096: tiny footprint
     j_big = make_job(he, ctxs, 2, 2, 701)       # conv 32->64 @8x8 at N=16384
-    # a cap that fits the big job alone but not two of them at once
-    cap = 100 << 20
+    # a cap that fits the big job alone (about 106 MB: its output and input
+    # buffers plus a workspace that either path can use) but not two at once
+    cap = 150 << 20
     srv = he.he_server_create(mem_cap_bytes=cap, slots=2, arena_bytes=256 << 20)
     outs = [he.empty_u64(tuple(j_big["out"].shape)) for _ in range(3)]
     tickets = [he.he_server_submit(srv, j_big["ctx"].h, j_big["plan"].h, j_big["d_ct"], j_big["d_w"], o) for o in outs]
