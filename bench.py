@@ -37,6 +37,31 @@ OPS_BFLY = OPS_MODMUL + 2
 OPS_MAC_TERM = OPS_MODMUL + 2   # quotient companion mul + accumulate add
 
 
+def kernel_src_sha():
+    """Digest of the library sources: hardware byte counts below are reported only
+    for the sources they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2409_16675_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# HBM bytes per persistent launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# passes over this benchmark (summaries under profiles/), each counter scaled by
+# what it reads for a plain 512 MiB device copy in the same run; keyed by the
+# digest of the sources the counters were taken on.
+TRAFFIC = {
+    # (source digest, layer jobs per launch): bytes per launch, with the counter readings
+    ("8244fb005d220b80", 5): {"bytes": 1017130268, "fetch_kib": 227132.1, "fetch_scale": 1.9999,
+                              "write_kib": 539053.0, "write_scale": 1.0,
+                              "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x5_hbm_bytes.md"},
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,7 +144,7 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
     ctx, plan = wl["ctx"], wl["plan"]
     stream = torch.cuda.current_stream()
 
-    def make(n):
+    def make(n, flags=he.HE_BATCH_GRAPH):
         b = he.he_batch_create(0)
         outs = []
         for j in range(n):
@@ -127,13 +152,14 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
             out = he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"]))
             he.he_batch_add(b, ctx.h, plan.h, lay["ct_in"], lay["w"], out, 0)
             outs.append(out)
-        he.he_batch_build(b, he.HE_BATCH_GRAPH)
+        he.he_batch_build(b, flags)
         return b, outs
 
     per_launch = max(1, min(per_launch, steps))
     full, rest = steps // per_launch, steps % per_launch
     b, outs = make(per_launch)
     br = make(rest) if rest else None
+    prof, _ = make(per_launch, he.HE_BATCH_PROFILE)
     for _ in range(warmup):
         he.he_batch_run(b, stream)
     he.he_batch_sync(b, stream)
@@ -148,11 +174,24 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     he.he_batch_sync(b, stream)
-    kern_ms = [a.elapsed_time(z) for a, z in ev]
+    launch_ms = [a.elapsed_time(z) for a, z in ev]
     info = he.he_batch_get_info(b)
     if br:
         he.he_batch_destroy(br[0])
-    return (t1 - t0) / steps, (sum(kern_ms) / len(kern_ms) if kern_ms else float("nan")), outs, b, info
+    # the persistent kernel alone: the same jobs launched directly, with HIP events
+    # recorded by the library on this stream right around the kernel (a graph
+    # replay also runs the control-word reset and the two cache-fence kernels)
+    he.he_batch_run(prof, stream)
+    he.he_batch_sync(prof, stream)
+    k0 = he.he_batch_get_info(prof)
+    for _ in range(max(1, full)):
+        he.he_batch_run(prof, stream)
+    he.he_batch_sync(prof, stream)
+    k1 = he.he_batch_get_info(prof)
+    he.he_batch_destroy(prof)
+    kern_ms = (k1["kernel_ms"] - k0["kernel_ms"]) / (k1["kernel_launches"] - k0["kernel_launches"])
+    info["graph_launch_ms"] = sum(launch_ms) / len(launch_ms) if launch_ms else float("nan")
+    return (t1 - t0) / steps, kern_ms, outs, b, info
 
 
 def ntt_rate(he, torch, wl, iters=20):
@@ -204,11 +243,14 @@ def roofline_persistent(wl, kern_ms, binfo):
     bytes_ = nj * (8 * N * (info["n_ct_in"] * 2 * L + info["n_ct_out"] * 2 * L) + 4 * 16 * 3 * 9)
     alu = ops / avg_s / 1e12
     hbm = bytes_ / avg_s / 1e9
+    tr = TRAFFIC.get((kernel_src_sha(), nj))
     return {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "T VALU-op/s",
-            "frac": round(alu / PEAK_VALU_TOPS, 4), "traffic": None,
+            "frac": round(alu / PEAK_VALU_TOPS, 4), "traffic": tr["bytes"] if tr else None,
+            "traffic_detail": tr,
             "kernel": "k_persistent (%d whole steps per launch: transforms, packing, MAC, inverse transforms)" % nj,
             "kernel_avg_us": round(avg_s * 1e6, 2), "ops_per_launch": int(ops), "alg_bytes_per_launch": int(bytes_),
-            "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
+            "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / PEAK_HBM_GBS, 4),
+            "graph_replay_avg_us": round(binfo["graph_launch_ms"] * 1e3, 2)}
 
 
 def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4, sweep=(20000.0, 100000.0)):
@@ -334,6 +376,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
         "path": "batched (persistent fused kernel, graph replay, %d layer jobs per launch)" % args.jobs_per_launch,
         "jobs_per_launch": args.jobs_per_launch,
+        "kernel_src_sha": kernel_src_sha(),
         "plain_value": round(n_cpmul / plain_dt, 1), "plain_ms_per_step": round(plain_dt * 1e3, 4),
         "fused_value": round(n_cpmul / fused_dt, 1), "fused_ms_per_step": round(fused_dt * 1e3, 4),
         "batched_equals_fused_equals_plain": same,

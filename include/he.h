@@ -102,7 +102,9 @@ he_status he_ctx_get_schedule(const he_ctx *ctx, uint32_t op, uint32_t *arith, u
 /* Autotuner: times every compiled schedule of the forward transform, the inverse
  * transform and the fused multiply-accumulate + inverse kernel on n_polys
  * polynomials of seeded data, keeps only candidates whose output is identical
- * to the reference schedule's, and installs the fastest in the context.  With
+ * to the reference schedule's, and installs the fastest in the context
+ * (candidates within 5% of the fastest count as a tie, broken in a fixed order:
+ * fp64 arithmetic first, then 16, 32, 8 coefficients per thread).  With
  * cache_path, a matching entry (device architecture, N, L, first prime) is read
  * instead of timing, and a new result is appended as one JSON line.  `report`
  * (optional, host) receives up to report_cap entries.  Allocates and frees
@@ -248,10 +250,16 @@ typedef struct {
   uint64_t fwd_planes;     /* forward plane transforms per run */
   uint64_t inv_planes;     /* inverse plane transforms per run */
   uint64_t ws_bytes;       /* device workspace owned by the batch */
+  uint64_t kernel_launches;   /* HE_BATCH_PROFILE: persistent-kernel launches timed so far */
+  double kernel_ms;           /* HE_BATCH_PROFILE: their total duration (HIP events around the kernel alone) */
 } he_batch_info;
 
 #define HE_BATCH_GRAPH 0x1u        /* capture the launch into a HIP graph (default on) */
 #define HE_BATCH_STRICT_SYNC 0x2u  /* every wave fences at every dependency (slower; for checking) */
+#define HE_BATCH_PROFILE 0x4u      /* direct launches only (not with HE_BATCH_GRAPH): HIP events on the run
+                                    * stream around the persistent kernel itself (not the control-word reset
+                                    * and cache-fence kernels beside it); he_batch_sync adds their durations
+                                    * to he_batch_info.kernel_ms.  At most 64 runs between two syncs. */
 
 /* Create an empty batch for `device` (host memory only). */
 he_status he_batch_create(int32_t device, he_batch **out);
@@ -263,7 +271,8 @@ he_status he_batch_add(he_batch *b, he_ctx *ctx, const he_job *job, uint32_t *in
 he_status he_batch_build(he_batch *b, uint32_t flags);
 /* Point job `index` at new buffers (same plan); no re-capture is needed. */
 he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job);
-/* Launch the whole batch on `stream` (asynchronous). */
+/* Launch the whole batch on `stream` (asynchronous).  HE_EINVAL with
+ * HE_BATCH_PROFILE after 64 runs without a sync. */
 he_status he_batch_run(he_batch *b, void *stream);
 /* Wait for `stream` and report HE_ETIMEOUT if a dependency wait hit its bound. */
 he_status he_batch_sync(he_batch *b, void *stream);

@@ -27,12 +27,19 @@ struct he_batch {
   hipGraphExec_t exec = nullptr;
   he_batch_info info{};
   uint32_t spin_limit = he::kSpinLimit;
+  // HE_BATCH_PROFILE: a ring of event pairs, read back at sync
+  static constexpr uint32_t kProfRing = 64;
+  std::vector<hipEvent_t> ev;          // 2 * kProfRing when profiling
+  uint32_t ev_next = 0, ev_pending = 0;
 };
 
 using namespace he;
 
 
 static void release(he_batch *b) {
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  b->ev.clear();
+  b->ev_next = b->ev_pending = 0;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -235,6 +242,14 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   info.arith = (uint32_t)b->arith;
   info.ws_bytes = b->ws_bytes;
   b->info = info;
+  if ((flags & HE_BATCH_PROFILE) && !(flags & HE_BATCH_GRAPH)) {
+    b->ev.resize(2 * he_batch::kProfRing, nullptr);
+    for (hipEvent_t &ev : b->ev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) {
+        release(b);
+        return hip_fail(e, "profiling events");
+      }
+  }
   if (flags & HE_BATCH_GRAPH) {
     if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
@@ -286,10 +301,18 @@ he_status he_batch_run(he_batch *b, void *stream) {
   if (!b || !b->built) return fail(HE_EINVAL, "batch not built");
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!b->ev.empty()) {
+    if (b->ev_pending >= he_batch::kProfRing) return fail(HE_EINVAL, "profiled batch: sync at least every 64 runs");
+    const uint32_t k = (b->ev_next + b->ev_pending) % he_batch::kProfRing;
+    e0 = b->ev[2 * k];
+    e1 = b->ev[2 * k + 1];
+  }
   if (b->exec) e = hipGraphLaunch(b->exec, st);
   else e = launch_persistent(b->var, b->d_tasks, b->n_tasks, b->xq, b->d_jobs, (uint32_t)b->jobs.size(), b->d_ctl,
-                             b->ctl_words, b->grid, b->spin_limit, b->strict, st);
+                             b->ctl_words, b->grid, b->spin_limit, b->strict, st, e0, e1);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
+  if (e0) b->ev_pending++;
   return HE_OK;
 }
 
@@ -297,6 +320,14 @@ he_status he_batch_sync(he_batch *b, void *stream) {
   if (!b || !b->built) return fail(HE_EINVAL, "batch not built");
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "batch sync");
+  for (; b->ev_pending; --b->ev_pending) {
+    const uint32_t k = b->ev_next;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, b->ev[2 * k], b->ev[2 * k + 1])) != hipSuccess) return hip_fail(e, "profiling events");
+    b->info.kernel_ms += ms;
+    b->info.kernel_launches++;
+    b->ev_next = (k + 1) % he_batch::kProfRing;
+  }
   uint32_t err = 0;
   e = hipMemcpy(&err, b->d_ctl + CTL_ERR, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "batch status");

@@ -63,8 +63,9 @@ bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pre
 struct XQ {
   uint32_t b[kXcds + 1];   // queue bounds in the task table
 };
+// ev0 / ev1 (optional): recorded on `st` right before and after the persistent kernel.
 hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
-                             uint32_t strict, hipStream_t st);
+                             uint32_t strict, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace he

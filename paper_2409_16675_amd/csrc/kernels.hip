@@ -31,8 +31,8 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   const uint64_t *src = in + (size_t)plane * G::N;
   uint64_t *dst = out + (size_t)plane * G::N;
   const int tid = threadIdx.x;
-  auto ld = [&](int k) { return ar.load(src[k]); };
-  auto st = [&](int k, uint64_t v) { dst[k] = v; };
+  auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
   ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
 }
 
@@ -52,8 +52,8 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   const int64_t *src = polys + (size_t)(plane / L) * G::N;
   uint64_t *dst = out + (size_t)plane * G::N;
   const int tid = threadIdx.x;
-  auto ld = [&](int k) { return ar.load_signed(src[k]); };
-  auto st = [&](int k, uint64_t v) { dst[k] = v; };
+  auto ld = [&](int k) { return ar.load_signed(src[(uint32_t)k]); };
+  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
   ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
 }
 
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = ar.load(src[j * G::NT + tid]);
-  auto st = [&](int k, uint64_t v) { dst[k] = v; };
+  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
   ntt_inverse_from_lds<A, G, 100>(ar, tw + (size_t)i * G::N, tid, lds, st);
 }
 
@@ -120,26 +120,22 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
   int t0, t1;
   term_range(ta, o, t0, t1);
   MacAcc<A> acc[G::E];
-  for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
-    const int te = min(t + MacAcc<A>::kChunk, t1);
-    for (int tt = t; tt < te; ++tt) {
-      const uint64_t *a = ct_hat + ((size_t)(term_ct(ta, tt) * 2 + comp) * L + i) * G::N;
-      const uint64_t *b = pt_hat + ((size_t)term_pt(ta, tt) * L + i) * G::N;
-      mac_term<A, G::E, G::NT>(ar, acc, a, b, tid);
-    }
-#pragma unroll
-    for (int j = 0; j < G::E; ++j) acc[j].fold(ar, *pk);
-  }
+  auto operands = [&](int t) {
+    const uint64_t *a = ct_hat + ((size_t)(term_ct(ta, t) * 2 + comp) * L + i) * G::N;
+    const uint64_t *b = pt_hat + ((size_t)term_pt(ta, t) * L + i) * G::N;
+    return std::pair<const uint64_t *, const uint64_t *>(a, b);
+  };
+  mac_terms<A, G::E, G::NT>(ar, *pk, acc, t0, t1, operands, tid);
 #pragma unroll
   for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = acc[j].value();
   uint64_t *dst = out + (size_t)plane * G::N;
   const uint64_t q = pk->q;
   if constexpr (ACC) {
-    auto st = [&](int k, uint64_t v) { dst[k] = canon_add(ar, dst[k], v, q); };
-    ntt_inverse_from_lds<A, G, 51>(ar, tw + (size_t)i * G::N, tid, lds, st);
+    auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = canon_add(ar, dst[(uint32_t)k], v, q); };
+    ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, tw + (size_t)i * G::N, tid, lds, st);
   } else {
-    auto st = [&](int k, uint64_t v) { dst[k] = v; };
-    ntt_inverse_from_lds<A, G, 51>(ar, tw + (size_t)i * G::N, tid, lds, st);
+    auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+    ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, tw + (size_t)i * G::N, tid, lds, st);
   }
 }
 

@@ -3,6 +3,8 @@
 // Sec. 3.3): acc[k] = sum_t ct_t[k] * pt_t[k] mod q, shared by the fused
 // multiply-accumulate + inverse-transform kernel and the persistent kernel.
 #pragma once
+#include <utility>
+
 #include "arith.hpp"
 
 namespace he {
@@ -16,7 +18,10 @@ template <>
 struct MacAcc<ArF64> {
   static constexpr int kChunk = 8;
   static constexpr int kLoadBatch = 32;   // coefficients whose operands are loaded together
+  static constexpr bool kLoneReduced = true;   // one product, unfolded, has |p| <= 0.76 q
+  static constexpr int kOutBoundX100 = 76;     // bound of value(): a lone product or a fold
   double acc = 0.0;
+  __device__ __forceinline__ void set(const ArF64 &ar, uint64_t a, uint64_t b) { acc = ar.mulv(ar.load(a), ar.load(b)); }
   __device__ __forceinline__ void add(const ArF64 &ar, uint64_t a, uint64_t b) { acc += ar.mulv(ar.load(a), ar.load(b)); }
   __device__ __forceinline__ void fold(const ArF64 &ar, const PrimeK &) { acc = ar.reduce(acc); }
   __device__ __forceinline__ double value() const { return acc; }
@@ -28,7 +33,13 @@ template <>
 struct MacAcc<ArU64> {
   static constexpr int kChunk = 15;
   static constexpr int kLoadBatch = 8;    // the 128-bit accumulators leave fewer registers
+  static constexpr bool kLoneReduced = false;  // a 128-bit product needs its fold
+  static constexpr int kOutBoundX100 = 100;    // canonical
   uint64_t lo = 0, hi = 0;
+  __device__ __forceinline__ void set(const ArU64 &, uint64_t a, uint64_t b) {
+    lo = a * b;
+    hi = __umul64hi(a, b);
+  }
   __device__ __forceinline__ void add(const ArU64 &, uint64_t a, uint64_t b) {
     const uint64_t pl = a * b, ph = __umul64hi(a, b);
     const uint64_t nl = lo + pl;
@@ -48,7 +59,8 @@ struct MacAcc<ArU64> {
 // One term for the E coefficients j * NT + tid of a thread: the operand loads
 // of a batch of coefficients are all issued before its first product, so they
 // are in flight together instead of one memory round trip per coefficient.
-template <class A, int E, int NT, class P>
+// FIRST: the accumulators take the products (no zero start).
+template <class A, int E, int NT, bool FIRST, class P>
 __device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, int tid) {
   constexpr int B = E < MacAcc<A>::kLoadBatch ? E : MacAcc<A>::kLoadBatch;
 #pragma unroll
@@ -62,7 +74,39 @@ __device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, 
       vb[j] = b[k];
     }
 #pragma unroll
-    for (int j = 0; j < B; ++j) acc[j0 + j].add(ar, va[j], vb[j]);
+    for (int j = 0; j < B; ++j) {
+      if constexpr (FIRST) acc[j0 + j].set(ar, va[j], vb[j]);
+      else acc[j0 + j].add(ar, va[j], vb[j]);
+    }
+  }
+}
+
+// The terms t0 .. t1-1 of one output plane; operands(t, a, b) yields the two
+// operand planes of term t.  Folds after every kChunk products; a last run of a
+// single product is left unfolded where that is within kOutBoundX100.  An empty
+// term list leaves the accumulators at zero.
+template <class A, int E, int NT, class Ops>
+__device__ __forceinline__ void mac_terms(const A &ar, const PrimeK &pk, MacAcc<A> *acc, int t0, int t1, Ops operands,
+                                          int tid) {
+  if (t0 >= t1) return;
+  {
+    auto [a, b] = operands(t0);
+    mac_term<A, E, NT, true>(ar, acc, a, b, tid);
+  }
+  int run = 1;   // products since the start or the last fold
+  for (int t = t0 + 1; t < t1; ++t) {
+    if (run == MacAcc<A>::kChunk) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) acc[j].fold(ar, pk);
+      run = 0;
+    }
+    auto [a, b] = operands(t);
+    mac_term<A, E, NT, false>(ar, acc, a, b, tid);
+    ++run;
+  }
+  if (run > 1 || !MacAcc<A>::kLoneReduced) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j].fold(ar, pk);
   }
 }
 

@@ -49,16 +49,18 @@ __device__ __forceinline__ HE_GLOBAL T *as_global(T *p) {
   return (HE_GLOBAL T *)p;
 }
 
-// One twiddle entry (16 bytes) through a generic or a global pointer.
+// One twiddle entry (16 bytes) through a generic or a global pointer.  The
+// byte offset is formed in 32 bits (tables are far below 4 GiB), so the load
+// is a scalar base plus a lane offset.
 template <class Tw>
-__device__ __forceinline__ Tw load_tw(const Tw *tw, int idx) {
-  return tw[idx];
+__device__ __forceinline__ Tw load_tw(const Tw *tw, uint32_t idx) {
+  return *(const Tw *)((const char *)tw + (size_t)(idx * (uint32_t)sizeof(Tw)));
 }
 template <class Tw>
-__device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, int idx) {
+__device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, uint32_t idx) {
   typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
   static_assert(sizeof(Tw) == sizeof(u64x2), "twiddle entries are 16 bytes");
-  const u64x2 v = *(const HE_GLOBAL u64x2 *)(tw + idx);
+  const u64x2 v = *(const HE_GLOBAL u64x2 *)((const HE_GLOBAL char *)tw + (size_t)(idx * (uint32_t)sizeof(Tw)));
   return __builtin_bit_cast(Tw, v);
 }
 
@@ -249,11 +251,12 @@ __device__ __forceinline__ void load_pass_tw(TwP tw, int tid, typename A::Tw (&t
   constexpr int NLOW = G::LOGN - S0 - R, NG = G::E >> R;
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
-    const int high = ((g << G::LOGT) | tid) >> NLOW;
+    const uint32_t high = (uint32_t)((g << G::LOGT) | tid) >> NLOW;
 #pragma unroll
     for (int u = 0; u < R; ++u)
 #pragma unroll
-      for (int j = 0; j < (1 << u); ++j) twr[g][(1 << u) - 1 + j] = load_tw(tw, (1 << (S0 + u)) + ((high << u) | j));
+      for (int j = 0; j < (1 << u); ++j)
+        twr[g][(1 << u) - 1 + j] = load_tw(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
   }
 }
 

@@ -53,20 +53,20 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   if (tk.kind == PT_FWD_CT) {
     const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
-    auto ld = [&](int k) { return ar.load(valid ? src[k] : 0ull); };
+    auto ld = [&](int k) { return ar.load(valid ? src[(uint32_t)k] : 0ull); };
     auto st = [&](int k, uint64_t v) {
-      if (valid) dst[k] = v;
+      if (valid) dst[(uint32_t)k] = v;
     };
     ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (tk.kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
     auto st = [&](int k, uint64_t v) {
-      if (valid) dst[k] = v;
+      if (valid) dst[(uint32_t)k] = v;
     };
     if (jb.pkind == PK_POLY) {
       const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
-      auto ld = [&](int k) { return ar.load_signed(valid ? src[k] : 0ll); };
+      auto ld = [&](int k) { return ar.load_signed(valid ? src[(uint32_t)k] : 0ll); };
       ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
@@ -111,16 +111,12 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     const HE_GLOBAL int32_t *cti = as_global(jb.cti), *pti = as_global(jb.pti);
     const HE_GLOBAL uint64_t *ct_hat = as_global((const uint64_t *)jb.ct_hat), *pt_hat = as_global((const uint64_t *)jb.pt_hat);
     MacAcc<A> acc[G::E];
-    for (int t = t0; t < t1; t += MacAcc<A>::kChunk) {
-      const int te = min(t + MacAcc<A>::kChunk, t1);
-      for (int tt = t; tt < te; ++tt) {
-        const HE_GLOBAL uint64_t *a = ct_hat + ((size_t)(cti[tt] * 2 + comp) * L + i) * G::N;
-        const HE_GLOBAL uint64_t *b = pt_hat + ((size_t)pti[tt] * L + i) * G::N;
-        mac_term<A, G::E, G::NT>(ar, acc, a, b, tid_g);
-      }
-#pragma unroll
-      for (int j = 0; j < G::E; ++j) acc[j].fold(ar, pk);
-    }
+    auto operands = [&](int t) {
+      const HE_GLOBAL uint64_t *a = ct_hat + ((size_t)(cti[t] * 2 + comp) * L + i) * G::N;
+      const HE_GLOBAL uint64_t *b = pt_hat + ((size_t)pti[t] * L + i) * G::N;
+      return std::pair<const HE_GLOBAL uint64_t *, const HE_GLOBAL uint64_t *>(a, b);
+    };
+    mac_terms<A, G::E, G::NT>(ar, pk, acc, t0, t1, operands, tid_g);
 #pragma unroll
     for (int j = 0; j < G::E; ++j) lds_g[lin_lds<G>(tid_g, j)] = acc[j].value();
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_out) + (size_t)plane * G::N;
@@ -130,16 +126,16 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     if (jb.accumulate) {
       auto st = [&](int k, uint64_t v) {
         if (valid) {
-          const uint64_t s = dst[k] + v;
-          dst[k] = s >= q ? s - q : s;
+          const uint64_t s = dst[(uint32_t)k] + v;
+          dst[(uint32_t)k] = s >= q ? s - q : s;
         }
       };
-      ntt_inverse_from_lds<A, G, 51>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
     } else {
       auto st = [&](int k, uint64_t v) {
-        if (valid) dst[k] = v;
+        if (valid) dst[(uint32_t)k] = v;
       };
-      ntt_inverse_from_lds<A, G, 51>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
     }
   }
 }
@@ -332,12 +328,13 @@ bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pre
 
 hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
-                             uint32_t strict, hipStream_t st) {
+                             uint32_t strict, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ctl, ctl_words);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
 #define HE_P(A, S, E, MN, MX) \
   launch_p<A, S, E, MN, MX>(tasks, n_tasks, xq, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
   if (v.arith == HE_ARITH_F64) {
@@ -356,6 +353,7 @@ hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_t
   }
 #undef HE_P
   if (e != hipSuccess) return e;
+  if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 1);
   return hipGetLastError();
 }

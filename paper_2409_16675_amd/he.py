@@ -307,7 +307,7 @@ def he_autotune(ctx, n_polys=512, cache_path=None, stream=None):
 
 
 # ------------------------------------------------------------------ batching
-HE_BATCH_GRAPH = 0x1
+HE_BATCH_GRAPH, HE_BATCH_STRICT_SYNC, HE_BATCH_PROFILE = 0x1, 0x2, 0x4
 
 
 class he_job(ctypes.Structure):
@@ -317,7 +317,8 @@ class he_job(ctypes.Structure):
 
 class he_batch_info(ctypes.Structure):
     _fields_ = [("n_jobs", c_u32), ("n_tasks", c_u32), ("grid", c_u32), ("arith", c_u32), ("cpmul", c_u64),
-                ("fwd_planes", c_u64), ("inv_planes", c_u64), ("ws_bytes", c_u64)]
+                ("fwd_planes", c_u64), ("inv_planes", c_u64), ("ws_bytes", c_u64), ("kernel_launches", c_u64),
+                ("kernel_ms", ctypes.c_double)]
 
 
 def _job(plan, ct_in, plain, ct_out, flags):

@@ -182,3 +182,23 @@ def test_single_degree_variants(gpu_lib, ctxs, loge):
             he.he_batch_destroy(b)
         finally:
             he.he_ctx_set_schedule(ctx.h, he.HE_OP_MAC, *saved)
+
+
+@pytest.mark.gpu
+def test_profiled_direct_launches(gpu_lib, ctxs):
+    # HE_BATCH_PROFILE times the persistent kernel with HIP events; results unchanged
+    he = gpu_lib
+    jobs = [make_job(he, ctxs, lay, 1, 400 + k) for k, lay in enumerate([0, 3])]
+    expect = [oracle_out(j) for j in jobs]
+    b = he.he_batch_create(0)
+    for j in jobs:
+        he.he_batch_add(b, j["ctx"].h, j["plan"].h, j["d_ct"], j["d_w"], j["out"], 0)
+    he.he_batch_build(b, he.HE_BATCH_PROFILE)
+    for _ in range(3):
+        he.he_batch_run(b)
+    he.he_batch_sync(b)
+    info = he.he_batch_get_info(b)
+    assert info["kernel_launches"] == 3 and info["kernel_ms"] > 0.0
+    for k, j in enumerate(jobs):
+        assert_equal_u64(he.to_numpy_u64(j["out"]), expect[k], "profiled job %d" % k)
+    he.he_batch_destroy(b)

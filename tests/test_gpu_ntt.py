@@ -118,9 +118,15 @@ def test_autotune_candidates_are_all_exact_and_chosen_one_is_installed(gpu_lib, 
     n_sched = len(he.compiled_schedules(N, f64_ok=bits <= 50))
     assert len(rep) == 3 * n_sched
     chosen = [he.he_ctx_get_schedule(ctx.h, op) for op in (he.HE_OP_FWD, he.HE_OP_INV, he.HE_OP_MAC)]
+    # the installed schedule: among the exact candidates within 5% of the fastest,
+    # the first in the fixed order (fp64 before integer, then 16, 32, 8 per thread)
+    def rank(r):
+        return (0 if r["arith"] == he.HE_ARITH_F64 else 10) + {4: 0, 5: 1, 3: 2}[r["loge"]]
     for op, (a, le) in enumerate(chosen):
-        best = min((r for r in rep if r["op"] == op), key=lambda r: r["us"])
-        assert (a, le) == (best["arith"], best["loge"])
+        cands = [r for r in rep if r["op"] == op]
+        fastest = min(r["us"] for r in cands)
+        pick = min((r for r in cands if r["us"] <= fastest * 1.05), key=rank)
+        assert (a, le) == (pick["arith"], pick["loge"])
     # a second context reads the cache instead of timing, and gets the same schedules
     ctx2 = he.Context(N, L, prime_bits=bits)
     assert he.he_autotune(ctx2.h, 64, cache) == []
