@@ -134,7 +134,9 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
     auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = canon_add(ar, dst[(uint32_t)k], v, q); };
     ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, tw + (size_t)i * G::N, tid, lds, st);
   } else {
-    auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+    // output planes are not read again here: streaming stores keep them from
+    // evicting the operands and twiddles that later planes reuse from L2
+    auto st = [&](int k, uint64_t v) { __builtin_nontemporal_store(v, &dst[(uint32_t)k]); };
     ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, tw + (size_t)i * G::N, tid, lds, st);
   }
 }

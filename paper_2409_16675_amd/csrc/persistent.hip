@@ -132,8 +132,9 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       };
       ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
     } else {
+      // streaming stores: output planes are not read again by this launch
       auto st = [&](int k, uint64_t v) {
-        if (valid) dst[(uint32_t)k] = v;
+        if (valid) __builtin_nontemporal_store(v, &dst[(uint32_t)k]);
       };
       ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
     }
