@@ -242,35 +242,46 @@ __device__ __forceinline__ typename A::V reduce_gs_in(const A &ar, typename A::V
 }
 
 // ------------------------------------------------------------------------ passes
-// Twiddle slot of stage u (of R) in a pass: the thread needs the 2^u entries
-// (1 << (S0 + u)) + (high << u) + j, j < 2^u, kept in slot (1 << u) - 1 + j.
-// All of a pass's twiddles are loaded before its data, so that their latency
-// overlaps the data loads (and, in LDS passes, the barrier).
-template <class A, class G, int S0, int R, class TwP>
-__device__ __forceinline__ void load_pass_tw(TwP tw, int tid, typename A::Tw (&twr)[G::E >> R][(1 << R) - 1]) {
-  constexpr int NLOW = G::LOGN - S0 - R, NG = G::E >> R;
+// Twiddles of pass K held in registers.  Stage u (of R) of the pass needs the
+// 2^u entries (1 << (S0 + u)) + (high << u) + j, j < 2^u, kept in slot
+// (1 << u) - 1 + j; an inverse pass starting at stage 0 also needs entries 0
+// and 1 (N^-1 folded in).  A pass's twiddles are loaded while the previous pass
+// is still running (between its arithmetic and its stores), so their latency
+// overlaps the stores, the barrier and the data loads.
+template <class A, class G, int K, bool INV>
+struct PassTw {
+  static constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R, NLOW = G::LOGN - S0 - R;
+  typename A::Tw w[NG][(1 << R) - 1];
+  typename A::Tw n0, n1;
+  template <class TwP>
+  __device__ __forceinline__ void load(TwP tw, int tid) {
 #pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    const uint32_t high = (uint32_t)((g << G::LOGT) | tid) >> NLOW;
+    for (int g = 0; g < NG; ++g) {
+      const uint32_t high = (uint32_t)((g << G::LOGT) | tid) >> NLOW;
 #pragma unroll
-    for (int u = 0; u < R; ++u)
+      for (int u = 0; u < R; ++u)
 #pragma unroll
-      for (int j = 0; j < (1 << u); ++j)
-        twr[g][(1 << u) - 1 + j] = load_tw(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+        for (int j = 0; j < (1 << u); ++j)
+          w[g][(1 << u) - 1 + j] = load_tw(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+    }
+    if constexpr (INV && S0 == 0) {
+      n0 = load_tw(tw, 0);
+      n1 = load_tw(tw, 1);
+    }
   }
-}
+};
 
 // Forward pass K.  ld(t, c) yields the value at plane index t + c, st(t, c, v)
-// stores it (t: thread part, c: compile-time part, see pass_index).
-template <class A, class G, int K, class TwP, class Ld, class St>
-__device__ __forceinline__ void fwd_pass(const A &ar, TwP tw, int tid, Ld ld, St st) {
+// stores it (t: thread part, c: compile-time part, see pass_index); mid() runs
+// after the arithmetic and before the stores.
+template <class A, class G, int K, class Ld, class St, class Mid>
+__device__ __forceinline__ void fwd_pass(const A &ar, const PassTw<A, G, K, false> &twr, int tid, Ld ld, St st,
+                                         Mid mid) {
   using V = typename A::V;
   constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
   constexpr PassPlan pp = plan_ct<A>(R, fwd_bound_in<A, G>(K));
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
   const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
-  typename A::Tw twr[NG][(1 << R) - 1];
-  load_pass_tw<A, G, S0, R>(tw, tid, twr);
   V v[G::E];
 #pragma unroll
   for (int g = 0; g < NG; ++g)
@@ -288,10 +299,11 @@ __device__ __forceinline__ void fwd_pass(const A &ar, TwP tw, int tid, Ld ld, St
       for (int p = 0; p < (1 << R); ++p) {
         if (p & (1 << (R - 1 - u))) continue;
         const int p2 = p | (1 << (R - 1 - u));
-        ar.ct(v[(g << R) | p], v[(g << R) | p2], twr[g][(1 << u) - 1 + (p >> (R - u))]);
+        ar.ct(v[(g << R) | p], v[(g << R) | p2], twr.w[g][(1 << u) - 1 + (p >> (R - u))]);
       }
     }
   }
+  mid();
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
@@ -299,21 +311,14 @@ __device__ __forceinline__ void fwd_pass(const A &ar, TwP tw, int tid, Ld ld, St
 }
 
 // Inverse pass K (stages S0+R-1 down to S0).  B0 is the bound of the transform's input.
-template <class A, class G, int K, int B0X100, class TwP, class Ld, class St>
-__device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St st) {
+template <class A, class G, int K, int B0X100, class Ld, class St, class Mid>
+__device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true> &twr, int tid, Ld ld, St st,
+                                         Mid mid) {
   using V = typename A::V;
   constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
   constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
   const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
-  typename A::Tw twr[NG][(1 << R) - 1];
-  load_pass_tw<A, G, S0, R>(tw, tid, twr);
-  // stage 0 folds N^-1 in: entries 0 and 1 of the inverse table
-  typename A::Tw tn0, tn1;
-  if constexpr (S0 == 0) {
-    tn0 = load_tw(tw, 0);
-    tn1 = load_tw(tw, 1);
-  }
   V v[G::E];
 #pragma unroll
   for (int g = 0; g < NG; ++g)
@@ -333,9 +338,9 @@ __device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St
         if (p & (1 << (R - 1 - u))) continue;
         const int p2 = p | (1 << (R - 1 - u));
         if (s == 0) {
-          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], tn0, tn1);
+          gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], twr.n0, twr.n1);
         } else {
-          gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], twr[g][(1 << u) - 1 + (p >> (R - u))]);
+          gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], twr.w[g][(1 << u) - 1 + (p >> (R - u))]);
         }
       }
     }
@@ -343,6 +348,7 @@ __device__ __forceinline__ void inv_pass(const A &ar, TwP tw, int tid, Ld ld, St
 #pragma unroll
   for (int e = 0; e < G::E; ++e)
     if ((pp.red[R] >> (e & ((1 << R) - 1))) & 1u) v[e] = ar.reduce(v[e]);
+  mid();
 #pragma unroll
   for (int g = 0; g < NG; ++g)
 #pragma unroll
@@ -364,53 +370,81 @@ struct LdsPut {
   __device__ __forceinline__ void operator()(int t, int c, V v) const { lds[lpad(t) + lpad_c(c)] = v; }
 };
 
-// Forward passes K..NPASS-1, LDS to LDS.
-template <class A, class G, int K, class TwP>
-__device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds) {
-  if constexpr (K < G::NPASS) {
-    __syncthreads();
-    fwd_pass<A, G, K>(ar, tw, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds});
-    fwd_lds_passes<A, G, K + 1>(ar, tw, tid, lds);
+// Forward passes K..NPASS-1, LDS to LDS; `cur` holds pass K's twiddles.  PF:
+// load the next pass's twiddles before this pass's stores (more registers
+// live across the barrier); otherwise after the barrier.
+template <class A, class G, int K, bool PF, class TwP>
+__device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds,
+                                               PassTw<A, G, K, false> &cur) {
+  __syncthreads();
+  if constexpr (!PF) cur.load(tw, tid);
+  if constexpr (K + 1 < G::NPASS) {
+    PassTw<A, G, K + 1, false> nxt;
+    fwd_pass<A, G, K>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
+      if constexpr (PF) nxt.load(tw, tid);
+    });
+    fwd_lds_passes<A, G, K + 1, PF>(ar, tw, tid, lds, nxt);
+  } else {
+    fwd_pass<A, G, K>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [] {});
   }
 }
 
-// Inverse passes K down to 1, LDS to LDS (pass 0 is run by the caller, to HBM).
-template <class A, class G, int K, int B0X100, class TwP>
-__device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds) {
-  if constexpr (K >= 1) {
-    __syncthreads();
-    inv_pass<A, G, K, B0X100>(ar, tw, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds});
-    inv_lds_passes<A, G, K - 1, B0X100>(ar, tw, tid, lds);
+// Inverse passes K down to 1, LDS to LDS; `cur` holds pass K's twiddles and
+// `last` receives pass 0's (pass 0 is run by the caller, to HBM).
+template <class A, class G, int K, int B0X100, bool PF, class TwP>
+__device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds,
+                                               PassTw<A, G, K, true> &cur, PassTw<A, G, 0, true> &last) {
+  __syncthreads();
+  if constexpr (!PF) cur.load(tw, tid);
+  if constexpr (K > 1) {
+    PassTw<A, G, K - 1, true> nxt;
+    inv_pass<A, G, K, B0X100>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
+      if constexpr (PF) nxt.load(tw, tid);
+    });
+    inv_lds_passes<A, G, K - 1, B0X100, PF>(ar, tw, tid, lds, nxt, last);
+  } else {
+    inv_pass<A, G, K, B0X100>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
+      if constexpr (PF) last.load(tw, tid);
+    });
   }
 }
 
 // Whole forward transform: ld2(t, c) reads coefficient t + c of the input
 // (coalesced pass-0 order), the result is written through st(i, canonical) in
 // linear order.
-template <class A, class G, class TwP, class Ld2, class St>
+template <class A, class G, bool PF = true, class TwP, class Ld2, class St>
 __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typename A::V *lds, Ld2 ld2, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
-  fwd_pass<A, G, 0>(ar, tw, tid, ld2, LdsPut<typename A::V>{lds});
-  fwd_lds_passes<A, G, 1>(ar, tw, tid, lds);
+  PassTw<A, G, 0, false> t0;
+  t0.load(tw, tid);
+  PassTw<A, G, 1, false> t1;
+  fwd_pass<A, G, 0>(ar, t0, tid, ld2, LdsPut<typename A::V>{lds}, [&] {
+    if constexpr (PF) t1.load(tw, tid);
+  });
+  fwd_lds_passes<A, G, 1, PF>(ar, tw, tid, lds, t1);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < G::E; ++j) st(j * G::NT + tid, ar.store(lds[lin_lds<G>(tid, j)]));
 }
 // The same with ld(i) reading coefficient i.
-template <class A, class G, class TwP, class Ld, class St>
+template <class A, class G, bool PF = true, class TwP, class Ld, class St>
 __device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typename A::V *lds, Ld ld, St st) {
-  ntt_forward_tc<A, G>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
+  ntt_forward_tc<A, G, PF>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
 }
 
 // Whole inverse transform of values already placed in LDS (linear order, bound
 // B0X100/100 q); pass 0 writes st(i, canonical) in coalesced order.
-template <class A, class G, int B0X100, class TwP, class St>
+template <class A, class G, int B0X100, bool PF = true, class TwP, class St>
 __device__ __forceinline__ void ntt_inverse_from_lds(const A &ar, TwP tw, int tid, typename A::V *lds, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
-  inv_lds_passes<A, G, G::NPASS - 1, B0X100>(ar, tw, tid, lds);
+  PassTw<A, G, G::NPASS - 1, true> first;
+  if constexpr (PF) first.load(tw, tid);
+  PassTw<A, G, 0, true> last;
+  inv_lds_passes<A, G, G::NPASS - 1, B0X100, PF>(ar, tw, tid, lds, first, last);
   __syncthreads();
+  if constexpr (!PF) last.load(tw, tid);
   auto st_out = [&](int t, int c, typename A::V v) { st(t + c, ar.store(v)); };
-  inv_pass<A, G, 0, B0X100>(ar, tw, tid, LdsAt<typename A::V>{lds}, st_out);
+  inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<typename A::V>{lds}, st_out, [] {});
 }
 
 }  // namespace he

@@ -57,7 +57,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     auto st = [&](int k, uint64_t v) {
       if (valid) dst[(uint32_t)k] = v;
     };
-    ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+    ntt_forward<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (tk.kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
@@ -67,7 +67,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     if (jb.pkind == PK_POLY) {
       const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
       auto ld = [&](int k) { return ar.load_signed(valid ? src[(uint32_t)k] : 0ll); };
-      ntt_forward<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+      ntt_forward<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
 #pragma unroll
@@ -99,7 +99,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
         }
       }
       __syncthreads();
-      ntt_forward_tc<A, G>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, LdsAt<typename A::V>{lds_g}, st);
+      ntt_forward_tc<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, LdsAt<typename A::V>{lds_g}, st);
     }
   } else {   // PT_MAC_INV: output plane (o, comp, i)
     const uint32_t comp = (plane / L) & 1, o = plane / (2 * L);
@@ -130,13 +130,13 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
           dst[(uint32_t)k] = s >= q ? s - q : s;
         }
       };
-      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100, false>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
     } else {
       // streaming stores: output planes are not read again by this launch
       auto st = [&](int k, uint64_t v) {
         if (valid) __builtin_nontemporal_store(v, &dst[(uint32_t)k]);
       };
-      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100, false>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
     }
   }
 }
@@ -306,13 +306,15 @@ static hipError_t launch_p(const PTask *tasks, uint32_t n_tasks, const XQ &xq, c
   return hipGetLastError();
 }
 
-// Variants compiled: F64 single-degree 4096/8192/16384 with 8, 16 or 32
-// coefficients per thread (the preferred count, normally the autotuned
-// multiply-accumulate schedule, where compiled; a workgroup has at most 1024
-// threads), and mixed-degree variants (16 per thread) for both arithmetics.
+// Variants compiled: F64 single-degree 4096/8192/16384 with 16 or 32
+// coefficients per thread (the preferred count -- normally the autotuned
+// multiply-accumulate schedule -- clamped to that range), and mixed-degree
+// variants (16 per thread) for both arithmetics.
 bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pref_loge, PVariant &v) {
   if (arith == HE_ARITH_F64 && logn_min == logn_max && logn_min >= 12 && logn_min <= 14) {
-    int loge = pref_loge < 3 ? 3 : (pref_loge > 5 ? 5 : pref_loge);
+    // 16 or 32 per thread: with 8, the task loop's own state leaves the
+    // 64-register budget short and the kernel spills
+    int loge = pref_loge < 4 ? 4 : (pref_loge > 5 ? 5 : pref_loge);
     if ((int)logn_min - loge > 10) loge = (int)logn_min - 10;
     v = PVariant{arith, (int)logn_min, loge, (int)logn_min, (int)logn_min};
   } else if (logn_max <= 13) {
@@ -339,10 +341,8 @@ hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_t
 #define HE_P(A, S, E, MN, MX) \
   launch_p<A, S, E, MN, MX>(tasks, n_tasks, xq, jobs, n_jobs, ctl, grid, spin_limit, strict, st)
   if (v.arith == HE_ARITH_F64) {
-    if (v.slab == 12 && v.logn_min == 12 && v.loge == 3) e = HE_P(ArF64, 12, 3, 12, 12);
-    else if (v.slab == 12 && v.logn_min == 12 && v.loge == 4) e = HE_P(ArF64, 12, 4, 12, 12);
+    if (v.slab == 12 && v.logn_min == 12 && v.loge == 4) e = HE_P(ArF64, 12, 4, 12, 12);
     else if (v.slab == 12 && v.logn_min == 12) e = HE_P(ArF64, 12, 5, 12, 12);
-    else if (v.slab == 13 && v.logn_min == 13 && v.loge == 3) e = HE_P(ArF64, 13, 3, 13, 13);
     else if (v.slab == 13 && v.logn_min == 13 && v.loge == 4) e = HE_P(ArF64, 13, 4, 13, 13);
     else if (v.slab == 13 && v.logn_min == 13) e = HE_P(ArF64, 13, 5, 13, 13);
     else if (v.slab == 14 && v.logn_min == 14 && v.loge == 4) e = HE_P(ArF64, 14, 4, 14, 14);

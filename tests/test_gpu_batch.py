@@ -156,9 +156,9 @@ def test_batched_conv_workload_and_transformed_inputs(gpu_lib, ctxs):
 @pytest.mark.parametrize("loge", [3, 4, 5])
 def test_single_degree_variants(gpu_lib, ctxs, loge):
     # a batch of one ring degree runs the single-degree persistent variant with the
-    # coefficients-per-thread of the context's multiply-accumulate schedule: every
-    # compiled count (8, 16, 32; the largest ring starts at 16) against the oracle,
-    # with a layer job and a multi-ciphertext FC job per ring
+    # coefficients-per-thread of the context's multiply-accumulate schedule, clamped
+    # to the compiled 16 and 32 (a schedule of 8 runs the 16 variant): every case
+    # against the oracle, with a layer job and a multi-ciphertext FC job per ring
     he = gpu_lib
     for ring, (N, L) in enumerate(synth.MIX_RINGS):
         ctx = ctxs[(N, L)]
