@@ -194,6 +194,30 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
     return (t1 - t0) / steps, kern_ms, outs, b, info
 
 
+def time_ppmul(he, torch, wl, steps, warmup):
+    """The server's plaintext product of the online protocol (Section 3.2) for the
+    same layer: masked input polynomials (16) times masked weight polynomials (16)
+    over Z_t[X]/(X^N+1), 256 outputs.  Returns seconds per layer."""
+    import numpy as np
+    ctx, plan, info, N = wl["ctx"], wl["plan"], wl["info"], wl["N"]
+    from paper_2409_16675_amd import synth
+    g = synth.rng(2, synth.STREAM_MASK)
+    t = ctx.t
+    a = he.to_device_u64(g.integers(0, t, size=(info["n_ct_in"], N), dtype=np.uint64))
+    b = he.to_device_u64(g.integers(0, t, size=(info["n_pt"], N), dtype=np.uint64))
+    out = he.empty_u64((info["n_ct_out"], N))
+    ws = he.workspace(he.he_ppmul_ws_size(plan.h, 0))
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        he.he_ppmul(ctx.h, plan.h, a, b, out, 0, ws, ws.numel(), stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        he.he_ppmul(ctx.h, plan.h, a, b, out, 0, ws, ws.numel(), stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
 def ntt_rate(he, torch, wl, iters=20):
     ctx = wl["ctx"]
     n_polys = 512
@@ -381,6 +405,7 @@ def main():
         "fused_value": round(n_cpmul / fused_dt, 1), "fused_ms_per_step": round(fused_dt * 1e3, 4),
         "batched_equals_fused_equals_plain": same,
         "ntt_per_s": round(ntt_rate(he, torch, wl), 1),
+        "ppmul_ms_per_layer": round(time_ppmul(he, torch, wl, max(5, args.steps // 2), args.warmup) * 1e3, 4),
         "kernels_fused_path": {k: dict(v, avg_us=round(v["total_ms"] * 1e3 / v["launches"], 2))
                                for k, v in stats.items()},
         "schedules": {k: {"arith": "f64" if v[0] == 1 else "u64", "coeffs_per_thread": 1 << v[1]}

@@ -211,6 +211,26 @@ he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys);
  * Hk = H + 2P - Hout + 1.  Values are taken as given (mod t after decryption). */
 he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *y);
 
+/* -------------------------------------------- plaintext product (PPMul) */
+/* The server's plaintext product of the online linear-layer protocol (Section
+ * 3.2): with the client's masked operands (x - r_x) and (w - r_w) it returns
+ * p = (x - r_x)(w - r_w), which the client subtracts from Dec(c) to obtain x w.
+ * Computed over the ring of the plaintext modulus, Z_t[X]/(X^N + 1), with the
+ * plan's term lists:
+ *   out[o] = sum over terms k of output o of a[cti[k]] * b[pti[k]]   (mod t)
+ * a    device [n_ct_in][N] residues in [0, t) (the input-side polynomials, e.g.
+ *      pi_x of the masked input block);
+ * b    device [n_pt][N] residues in [0, t) (the weight-side polynomials);
+ * out  device [n_ct_out][N], written, residues in [0, t).
+ * Needs t prime with t = 1 mod 2N (65537 serves every N <= 2^15), else
+ * HE_EUNSUPPORTED; the transforms of that ring are built on first use (device
+ * memory owned by the context).  flags: HE_VALIDATE (HE_ERANGE if an input is
+ * not below t).  ws: device, he_ppmul_ws_size() bytes.  Asynchronous on
+ * `stream` unless validating. */
+he_status he_ppmul_ws_size(const he_plan *plan, uint32_t flags, size_t *bytes);
+he_status he_ppmul(he_ctx *ctx, const he_plan *plan, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                   uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
 /* ----------------------------------------------- test-only encryption (client) */
 
 /* BFV-style secret-key encryption (a reading of Section 2 "HE", which encrypts

@@ -192,6 +192,76 @@ static he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes,
   return HE_OK;
 }
 
+// ---------------------------------------------------------------- plaintext product
+// The ring of the plaintext modulus: one prime q = t (an NTT-friendly t such
+// as 65537 = 2^16 + 1 is 1 mod 2N for every N <= 2^15), built on first use.
+static he_status t_ring(Ctx &c, Ctx **out) {
+  std::lock_guard<std::mutex> g(c.tctx_mu);
+  if (!c.tctx) {
+    const uint64_t q = c.t;
+    he_params p{};
+    p.N = c.N;
+    p.L = 1;
+    p.arith = HE_ARITH_F64;
+    p.q = &q;
+    p.t = 3;          // unused by the plaintext ring; any value coprime to q
+    p.device = c.device;
+    Ctx *tc = nullptr;
+    if (build_context(&p, &tc) != HE_OK)
+      return fail(HE_EUNSUPPORTED, "the plaintext product needs t prime with t = 1 mod 2N");
+    c.tctx = tc;
+  }
+  *out = c.tctx;
+  return HE_OK;
+}
+
+static size_t al256p(size_t b) { return (b + 255) & ~(size_t)255; }
+
+he_status he_ppmul_ws_size(const he_plan *plan, uint32_t flags, size_t *bytes) {
+  if (!plan || !bytes) return fail(HE_EINVAL, "null argument");
+  const he_plan_info &in = plan->p.info;
+  const size_t plane = (size_t)plan->ctx->N * 8;
+  *bytes = al256p((size_t)in.n_ct_in * plane) + al256p((size_t)in.n_pt * plane) + ((flags & HE_VALIDATE) ? 256 : 0);
+  return HE_OK;
+}
+
+he_status he_ppmul(he_ctx *ctx, const he_plan *plan, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                   uint32_t flags, void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx || !plan || !out || !a || !b) return fail(HE_EINVAL, "null argument");
+  if (plan->ctx != ctx->c) return fail(HE_EINVAL, "plan belongs to another context");
+  if (flags & ~HE_VALIDATE) return fail(HE_EINVAL, "flags: only HE_VALIDATE applies");
+  Ctx &c = *ctx->c;
+  const Plan &p = plan->p;
+  const he_plan_info &in = p.info;
+  size_t need = 0;
+  he_ppmul_ws_size(plan, flags, &need);
+  if (ws_bytes < need || (need && !ws)) return fail(HE_ENOMEM, "workspace too small");
+  Ctx *tc = nullptr;
+  he_status rs = t_ring(c, &tc);
+  if (rs != HE_OK) return rs;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  uint64_t *a_hat = (uint64_t *)w;
+  uint64_t *b_hat = (uint64_t *)(w + al256p((size_t)in.n_ct_in * c.N * 8));
+  if (flags & HE_VALIDATE) {
+    he_status s = validate(*tc, a, in.n_ct_in, w + need - 256, st);
+    if (s == HE_OK) s = validate(*tc, b, in.n_pt, w + need - 256, st);
+    if (s != HE_OK) return s;
+  }
+  // the context's tuned thread counts, fp64 arithmetic (t < 2^32)
+  const Sched sf{HE_ARITH_F64, c.s_fwd.loge}, sm{HE_ARITH_F64, c.s_mac.loge};
+  Terms tm;
+  tm.row = p.d_row();
+  tm.cti = p.d_cti();
+  tm.pti = p.d_pti();
+  tm.n_out = in.n_ct_out;
+  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*tc, sf, a_hat, a, in.n_ct_in, st); }), "ppmul forward a");
+  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*tc, sf, b_hat, b, in.n_pt, st); }), "ppmul forward b");
+  HIPCHK(timed(c, st, KK_MAC_INV, [&] { return launch_mac(*tc, sm, out, a_hat, b_hat, tm, false, false, st, 1); }),
+         "ppmul multiply + inverse");
+  return HE_OK;
+}
+
 he_status he_cpmul_acc(he_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint32_t K, uint64_t *acc, uint32_t flags,
                        void *ws, size_t ws_bytes, void *stream) {
   if (!ctx || !acc || (K && (!ct || !pt))) return fail(HE_EINVAL, "null argument");

@@ -200,6 +200,7 @@ he_status build_context(const he_params *p, Ctx **out) {
 
 void free_context(Ctx *c) {
   if (!c) return;
+  if (c->tctx) free_context(c->tctx);
   (void)hipSetDevice(c->device);
   for (void *p : {(void *)c->d_primes, c->d_tw_f64_fwd, c->d_tw_f64_inv, c->d_tw_u64_fwd, c->d_tw_u64_inv})
     if (p) (void)hipFree(p);

@@ -42,6 +42,10 @@ struct Ctx {
   mutable std::vector<ProfRec> prof;
   // schedules chosen per operation (autotuner may change them)
   Sched s_fwd{HE_ARITH_U64, 4}, s_inv{HE_ARITH_U64, 4}, s_mac{HE_ARITH_U64, 4};
+  // ring of the plaintext modulus (one prime, q = t), built on first use by
+  // the plaintext product; owned by this context
+  Ctx *tctx = nullptr;
+  std::mutex tctx_mu;
 };
 
 enum KernelKind { KK_FWD = 0, KK_FWD_LIFT = 1, KK_INV = 2, KK_MAC_INV = 3, KK_MAC = 4, KK_PACK = 5, KK_PERSIST = 6 };
@@ -86,8 +90,10 @@ struct Terms {
   uint32_t n_out = 1;
   uint32_t K = 0;   // identity mode only
 };
+// ncomp: components per operand (2: ciphertext x plaintext; 1: plaintext x
+// plaintext, fused inverse only, no accumulate).
 hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct_hat, const uint64_t *pt_hat,
-                      const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st);
+                      const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st, int ncomp = 2);
 
 hipError_t launch_zero_i64(int64_t *p, size_t n, hipStream_t st);
 hipError_t launch_pack_conv_w(int64_t *polys, const int32_t *w, uint32_t M, uint32_t C, uint32_t h, uint32_t O,

@@ -1,5 +1,7 @@
 // gfx950 kernels of libhe.so: transforms, fused multiply-accumulate + inverse
 // transform, plaintext packing, and the small helpers used by encryption.
+#include <type_traits>
+
 #include "he_internal.hpp"
 #include "ntt.hpp"
 #include "mac.hpp"
@@ -99,7 +101,9 @@ __device__ __forceinline__ int term_pt(const TermArgs &ta, int t) { return ta.ro
 
 // One workgroup per output plane (o, comp, i): multiply-accumulate the slots in
 // linear order into LDS, then the inverse transform, then store (or add).
-template <class A, int LOGN, int LOGT, bool ACC>
+// NCOMP: components per operand and output (2 for ciphertexts; 1 for products
+// of plaintext polynomials).
+template <class A, int LOGN, int LOGT, bool ACC, int NCOMP = 2>
 __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_mac_inv(
     uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat, const uint64_t *__restrict__ pt_hat, TermArgs ta,
     const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, int L, uint32_t xcd_chunk,
@@ -109,11 +113,11 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
   // Workgroups are dealt round-robin over the 8 XCDs; give XCD x a contiguous
   // run of output planes so that outputs sharing inputs share that XCD's L2.
-  const int plane = (int)((blockIdx.x & 7u) * xcd_chunk + (blockIdx.x >> 3));   // (o * 2 + comp) * L + i
+  const int plane = (int)((blockIdx.x & 7u) * xcd_chunk + (blockIdx.x >> 3));   // (o * NCOMP + comp) * L + i
   if (plane >= n_planes) return;
   const int i = plane % L;
-  const int comp = (plane / L) & 1;
-  const int o = plane / (2 * L);
+  const int comp = NCOMP == 1 ? 0 : (plane / L) % NCOMP;
+  const int o = plane / (NCOMP * L);
   const PrimeK *pk = primes + i;
   const A ar(*pk);
   const int tid = threadIdx.x;
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
   term_range(ta, o, t0, t1);
   MacAcc<A> acc[G::E];
   auto operands = [&](int t) {
-    const uint64_t *a = ct_hat + ((size_t)(term_ct(ta, t) * 2 + comp) * L + i) * G::N;
+    const uint64_t *a = ct_hat + ((size_t)(term_ct(ta, t) * NCOMP + comp) * L + i) * G::N;
     const uint64_t *b = pt_hat + ((size_t)term_pt(ta, t) * L + i) * G::N;
     return std::pair<const uint64_t *, const uint64_t *>(a, b);
   };
@@ -320,6 +324,7 @@ struct LaunchArgs {
   const uint64_t *pt;
   TermArgs ta;
   int accumulate;
+  int ncomp;
   unsigned grid;
 };
 
@@ -347,7 +352,16 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
     case OP_MAC_INV: {
       const uint32_t chunk = (la.grid + 7) / 8;
       const unsigned grid = chunk * 8;
-      if (la.accumulate) {
+      if (la.ncomp == 1) {
+        // single-component products (plaintext polynomials): fp64 arithmetic only
+        if constexpr (std::is_same_v<A, ArF64>) {
+          if ((e = prep(k_mac_inv<A, LOGN, LOGT, false, 1>, lds)) != hipSuccess) return e;
+          hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false, 1>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in,
+                             la.pt, la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
+        } else {
+          return hipErrorInvalidValue;
+        }
+      } else if (la.accumulate) {
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, true>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, true>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
                            la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
@@ -444,9 +458,11 @@ hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uin
 }
 
 hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct_hat, const uint64_t *pt_hat,
-                      const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st) {
+                      const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st, int ncomp) {
   TermArgs ta{tm.row, tm.cti, tm.pti, tm.K};
-  const uint32_t n_planes = tm.n_out * 2 * c.L;
+  const uint32_t n_planes = tm.n_out * (uint32_t)ncomp * c.L;
+  if (ncomp != 1 && ncomp != 2) return hipErrorInvalidValue;
+  if (ncomp == 1 && (out_ntt || accumulate)) return hipErrorInvalidValue;
   if (n_planes == 0) return hipSuccess;
   if (out_ntt) {
     dim3 grid((c.N + 255) / 256, n_planes);
@@ -464,6 +480,7 @@ hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_
   la.pt = pt_hat;
   la.ta = ta;
   la.accumulate = accumulate ? 1 : 0;
+  la.ncomp = ncomp;
   la.grid = n_planes;
   return dispatch(c, s, OP_MAC_INV, la, st);
 }

@@ -67,6 +67,8 @@ _SIGS = {
     "he_plan_terms": [c_void_p, i32p, i32p, i32p],
     "he_workspace_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
     "he_corr_conv2d": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
+    "he_ppmul_ws_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
+    "he_ppmul": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
     "he_pack_input": [c_void_p, i32p, i64p],
     "he_extract_output": [c_void_p, i64p, i64p],
     "he_encrypt": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -265,6 +267,18 @@ def he_workspace_size(plan, flags=0):
 def he_corr_conv2d(ctx, plan, ct_in, plain, ct_out, flags=0, ws=None, ws_bytes=0, stream=None):
     _chk(_lib.he_corr_conv2d(ctx, plan, _ptr(ct_in), _ptr(plain), _ptr(ct_out), flags, _ptr(ws), ws_bytes,
                              _stream(stream)), "he_corr_conv2d")
+
+
+def he_ppmul_ws_size(plan, flags=0):
+    b = c_size()
+    _chk(_lib.he_ppmul_ws_size(plan, flags, ctypes.byref(b)), "he_ppmul_ws_size")
+    return b.value
+
+
+def he_ppmul(ctx, plan, a, b, out, flags=0, ws=None, ws_bytes=0, stream=None):
+    """out[o] = sum over the plan's terms of a[cti] * b[pti] in Z_t[X]/(X^N+1) (device buffers)."""
+    _chk(_lib.he_ppmul(ctx, plan, _ptr(a), _ptr(b), _ptr(out), flags, _ptr(ws), ws_bytes, _stream(stream)),
+         "he_ppmul")
 
 
 def he_pack_input(plan, x, n_out_words):

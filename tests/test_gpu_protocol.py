@@ -1,0 +1,155 @@
+"""GPU parity of the online linear-layer protocol of Section 3.2: the plaintext
+product p = (x - r_x)(w - r_w) over Z_t[X]/(X^N+1) (he_ppmul) against the
+oracle's ring product mod t, and the whole exchange
+    c = [x] (x) (w - r_w) + [w] (x) (x - r_x) + [r_x r_w],   Dec(c) - p = x w
+run on the device and checked against the plaintext convolution."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bfv, core, packing, plain
+from paper_2409_16675_amd import synth
+from tests.helpers import assert_equal_u64
+
+T = synth.T_PLAIN
+
+
+def _oracle_ppmul(a, b, row, cti, pti):
+    out = []
+    for o in range(len(row) - 1):
+        acc = np.zeros(a.shape[-1], dtype=np.int64)
+        for k in range(row[o], row[o + 1]):
+            acc = (acc + core.negacyclic_mul(a[cti[k]], b[pti[k]], T).astype(np.int64)) % T
+        out.append(acc.astype(np.uint64))
+    return np.stack(out)
+
+
+def _ppmul(he, ctx, plan, a, b, flags=0):
+    info = plan.info
+    out = he.empty_u64((info["n_ct_out"], ctx.N))
+    ws = he.workspace(he.he_ppmul_ws_size(plan.h, flags))
+    he.he_ppmul(ctx.h, plan.h, he.to_device_u64(a), he.to_device_u64(b), out, flags, ws, ws.numel())
+    torch.cuda.synchronize()
+    return he.to_numpy_u64(out)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,B,C,M,H,h,P", [(1024, 2, 2, 3, 2, 6, 3, 1), (4096, 2, 1, 16, 4, 16, 3, 1),
+                                             (2048, 2, 2, 40, 3, 6, 3, 1)])
+def test_ppmul_matches_oracle(gpu_lib, N, L, B, C, M, H, h, P):
+    # every output against the ring product mod t, over the plan's term lists
+    # (the last shape has several channel blocks, so several terms per output)
+    he = gpu_lib
+    ctx = he.Context(N, L)
+    plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    info = plan.info
+    g = synth.rng(50, synth.STREAM_PT, N + C)
+    a = g.integers(0, T, size=(info["n_ct_in"], N), dtype=np.uint64)
+    b = g.integers(0, T, size=(info["n_pt"], N), dtype=np.uint64)
+    a[0, :4] = [0, 1, T - 1, T - 2]          # edge residues
+    b[0, :4] = [T - 1, T - 1, 0, 1]
+    row, cti, pti = packing.conv_terms(B, M, info["cb"])
+    print("case ppmul N=%d C=%d cb=%d" % (N, C, info["cb"]), flush=True)
+    assert_equal_u64(_ppmul(he, ctx, plan, a, b), _oracle_ppmul(a, b, row, cti, pti), "ppmul")
+
+
+@pytest.mark.gpu
+def test_ppmul_at_the_conv_workload_size(gpu_lib):
+    # N = 8192, batch 16 x 3 -> 16 channels: 256 outputs, sampled coefficients
+    # against the oracle's single-coefficient ring product mod t
+    he = gpu_lib
+    ctx = he.Context(8192, 3, prime_bits=50)
+    plan = he.Plan(ctx, he.HE_KIND_CONV, B=16, C=3, M=16, H=32, W=32, h=3, P=1)
+    g = synth.rng(51, synth.STREAM_PT)
+    a = g.integers(0, T, size=(16, 8192), dtype=np.uint64)
+    b = g.integers(0, T, size=(16, 8192), dtype=np.uint64)
+    got = _ppmul(he, ctx, plan, a, b)
+    rs = np.random.Generator(np.random.PCG64(52))
+    for _ in range(40):
+        o, k = int(rs.integers(256)), int(rs.integers(8192))
+        bi, m = divmod(o, 16)
+        assert int(got[o, k]) == core.negacyclic_coeff(a[bi], b[m], T, k), (o, k)
+
+
+@pytest.mark.gpu
+def test_ppmul_errors(gpu_lib):
+    he = gpu_lib
+    ctx = he.Context(1024, 2)
+    plan = he.Plan(ctx, he.HE_KIND_CONV, B=1, C=1, M=1, H=4, W=4, h=3, P=1)
+    a = np.zeros((1, 1024), dtype=np.uint64)
+    b = np.zeros((1, 1024), dtype=np.uint64)
+    a[0, 7] = T                               # not below t
+    with pytest.raises(he.HeError) as ei:
+        _ppmul(he, ctx, plan, a, b, he.HE_VALIDATE)
+    assert ei.value.status == he.HE_ERANGE
+    # a plaintext modulus without a negacyclic transform of this degree
+    ctx2 = he.Context(1024, 2, t=65536)
+    plan2 = he.Plan(ctx2, he.HE_KIND_CONV, B=1, C=1, M=1, H=4, W=4, h=3, P=1)
+    with pytest.raises(he.HeError) as ei:
+        _ppmul(he, ctx2, plan2, np.zeros((1, 1024), np.uint64), np.zeros((1, 1024), np.uint64))
+    assert ei.value.status == he.HE_EUNSUPPORTED
+
+
+@pytest.mark.gpu
+def test_online_protocol_end_to_end(gpu_lib):
+    # client packs, masks and encrypts; server runs the two CPMul-accumulates
+    # (second with the operand roles swapped), the CCAdd of [r_x r_w] and the
+    # plaintext product on the device; client: Dec(c) - p, extracted, equals the
+    # plaintext convolution mod t
+    he = gpu_lib
+    N, L, B, C, M, H, h, P = 1024, 2, 2, 3, 2, 6, 3, 1
+    ctx = he.Context(N, L)
+    plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    info = plan.info
+    geo = packing.ConvGeometry(C, H, H, h, P, N)
+    assert info["cb"] == geo.cb == 1
+    g = synth.rng(53, synth.STREAM_ACT)
+    x = synth.int8_uniform(g, (B, C, H, H))
+    w = synth.int8_uniform(g, (M, C, h, h))
+    xh = np.remainder(np.concatenate([packing.pack_conv_input(x[b], geo) for b in range(B)]), T)    # [B, N]
+    wh = np.remainder(packing.pack_conv_weight(w, geo).reshape(-1, N), T)                           # [M, N]
+    rx = g.integers(0, T, size=xh.shape)
+    rw = g.integers(0, T, size=wh.shape)
+    xm, wm = np.remainder(xh - rx, T), np.remainder(wh - rw, T)
+    # client-side encryptions (oracle): [x], [w], [r_x r_w] per output
+    s = synth.ternary(synth.rng(53, synth.STREAM_SK), N)
+    ga, ge = synth.rng(53, synth.STREAM_A), synth.rng(53, synth.STREAM_E)
+
+    def enc(m):
+        return bfv.encrypt(np.remainder(m, T), s, synth.uniform_residues(ga, (), ctx.q, N), synth.small_error(ge, N),
+                           ctx.q, ctx.psi, T)
+
+    ct_x = np.stack([enc(p) for p in xh])
+    ct_w = np.stack([enc(p) for p in wh])
+    ct_rr = np.stack([enc(core.negacyclic_mul(rx[b], rw[m], T)) for b in range(B) for m in range(M)])
+    # server, on the device
+    c = he.to_device_u64(ct_rr)                                   # CCAdd target, starts at [r_x r_w]
+    ws = he.workspace(plan.workspace_size(he.HE_PLAIN_POLY | he.HE_ACCUMULATE))
+    he.he_corr_conv2d(ctx.h, plan.h, he.to_device_u64(ct_x), torch.from_numpy(wm.astype(np.int64)).cuda(), c,
+                      he.HE_PLAIN_POLY | he.HE_ACCUMULATE, ws, ws.numel())       # + [x] (x) (w - r_w)
+    d_ctw = he.to_device_u64(ct_w)
+    d_xm = he.to_device_u64(core.lift(xm, ctx.q))                # [B, L, N]
+    ws2 = he.workspace(he.he_cpmul_acc_ws(ctx.h, 1, he.HE_ACCUMULATE))
+    for b in range(B):
+        for m in range(M):
+            he.he_cpmul_acc(ctx.h, d_ctw[m], d_xm[b], 1, c[b * M + m], he.HE_ACCUMULATE, ws2, ws2.numel())  # + [w] (x) (x - r_x)
+    p = _ppmul(he, ctx, plan, xm.astype(np.uint64), wm.astype(np.uint64))
+    torch.cuda.synchronize()
+    got_c = he.to_numpy_u64(c)
+    # the ciphertext part against the oracle's own run of the same exchange
+    row, cti, pti = packing.conv_terms(B, M, 1)
+    t1 = core.csr_cpmul(ct_x, core.lift(wm, ctx.q), row, cti, pti, ctx.q, ctx.psi)
+    t2 = core.csr_cpmul(ct_w, core.lift(xm, ctx.q), row, pti, cti, ctx.q, ctx.psi)
+    qa = np.array(ctx.q, dtype=object)[None, None, :, None]
+    expect_c = ((t1.astype(object) + t2.astype(object) + ct_rr.astype(object)) % qa).astype(np.uint64)
+    assert_equal_u64(got_c, expect_c, "protocol ciphertext")
+    assert_equal_u64(p, _oracle_ppmul(xm, wm, row, cti, pti), "protocol plaintext product")
+    # client
+    for b in range(B):
+        for m in range(M):
+            o = b * M + m
+            d = (bfv.decrypt(got_c[o], s, ctx.q, ctx.psi, T).astype(np.int64) - p[o].astype(np.int64)) % T
+            y = he.he_extract_output(plan.h, np.tile(d, (B, M, 1)).reshape(-1), B * M * (H + 2 * P - h + 1) ** 2)
+            y = y.reshape(B, M, H + 2 * P - h + 1, -1)[0, 0]
+            ref = plain.mod_t(plain.conv2d(x[b], w[m:m + 1], P)[0], T)
+            assert np.array_equal(np.remainder(y, T), ref), (b, m)
