@@ -46,6 +46,8 @@ def lib():
             "orc_ntt_planes": (None, [u64p, U32, U32, U32, u64p, u64p, u64p, ctypes.c_int]),
             "orc_negacyclic_mul_planes": (None, [u64p, u64p, U32, U32, U32, u64p, u64p]),
             "orc_num_threads": (ctypes.c_int, []),
+            "orc_philox4x64": (None, [u64p, u64p, u64p]),
+            "orc_expand_c1": (None, [U64, U64, U64, u64p, U32, U32, u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -222,3 +224,21 @@ def lift(values, q):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def philox4x64(counter, key):
+    """Philox4x64-10 of a 4-word counter under a 2-word key -> 4 words (uint64)."""
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64(c.ctypes.data_as(u64p), k.ctypes.data_as(u64p), out.ctypes.data_as(u64p))
+    return out
+
+
+def expand_c1(seed, j, q, N):
+    """Component 1 of ciphertext j regenerated from the 2-word seed: [L, N] residues."""
+    qa = np.ascontiguousarray(q, dtype=np.uint64)
+    out = np.zeros((len(q), N), dtype=np.uint64)
+    lib().orc_expand_c1(int(seed[0]), int(seed[1]), int(j), qa.ctypes.data_as(u64p), len(q), N,
+                        out.ctypes.data_as(u64p))
+    return out

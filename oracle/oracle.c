@@ -350,6 +350,53 @@ void orc_negacyclic_mul_planes(const uint64_t *a, const uint64_t *b, uint32_t n,
     orc_negacyclic_mul(a + (size_t)w * N, b + (size_t)w * N, N, q[w % L], out + (size_t)w * N);
 }
 
+/* ---------------------------------------------------------------- seeded c1
+ * The client may send a seed instead of the uniform ciphertext component c1,
+ * the server regenerating c1 from it (Section 6, discussion of upload cost).
+ * Generator: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC 2011), a counter-based bijection of a
+ * 256-bit counter under a 128-bit key: ten rounds, each multiplying two
+ * counter words by fixed odd constants into 128-bit products and mixing their
+ * halves with the other two words and the key, the key stepping by two Weyl
+ * constants between rounds.
+ * Reading (not in the paper): coefficient k of component 1 of ciphertext j at
+ * prime i is (w0 * 2^64 + w1) mod q_i with (w0, w1, w2, w3) =
+ * Philox4x64-10(counter (k, j, i, 0), key (seed0, seed1)); 128 random bits
+ * per residue keep the distance from uniform below 2^-78. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    const u128 p0 = (u128)M0 * c0, p1 = (u128)M1 * c2;
+    const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c1 ^ k0, n1 = (uint64_t)p1;
+    const uint64_t n2 = (uint64_t)(p0 >> 64) ^ c3 ^ k1, n3 = (uint64_t)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* out [L][N]: component 1 of ciphertext j regenerated from the seed */
+void orc_expand_c1(uint64_t seed0, uint64_t seed1, uint64_t j, const uint64_t *q, uint32_t L, uint32_t N,
+                   uint64_t *out) {
+  const uint64_t key[2] = {seed0, seed1};
+  for (uint32_t i = 0; i < L; ++i)
+    for (uint32_t k = 0; k < N; ++k) {
+      const uint64_t ctr[4] = {k, j, i, 0};
+      uint64_t w[4];
+      orc_philox4x64(ctr, key, w);
+      out[(size_t)i * N + k] = (uint64_t)((((u128)w[0] << 64) | w[1]) % q[i]);
+    }
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   extern int omp_get_max_threads(void);
