@@ -203,6 +203,23 @@ he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes);
 he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in, const void *plain,
                          uint64_t *ct_out, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
+/* Seeded component c1 (Section 6: the client sends a seed instead of the
+ * uniform c1; about half the upload).  Coefficient k of component 1 of
+ * ciphertext j at prime i is (w0 2^64 + w1) mod q_i, where (w0, w1, w2, w3) is
+ * the Philox4x64-10 block (Salmon et al., SC 2011) of counter (k, j, i, 0)
+ * under key (seed[0], seed[1]).
+ * he_corr_conv2d_seeded: as he_corr_conv2d, with ct0 device [n_ct_in][L][N]
+ * (component 0 of each input ciphertext) and seed host [2]; component 1 of
+ * input j is regenerated inside the forward transform (never stored or read).
+ * HE_IN_NTT is refused (HE_EINVAL); HE_VALIDATE checks ct0.
+ * he_expand_c1: writes component 1 of ciphertexts first_ct .. first_ct+n_ct-1
+ * to out, device [n_ct][L][N] (the client uses it to encrypt). */
+he_status he_corr_conv2d_seeded(he_ctx *ctx, const he_plan *plan, const uint64_t *ct0, const uint64_t *seed,
+                                const void *plain, uint64_t *ct_out, uint32_t flags, void *ws, size_t ws_bytes,
+                                void *stream);
+he_status he_expand_c1(he_ctx *ctx, const uint64_t *seed, uint32_t first_ct, uint32_t n_ct, uint64_t *out,
+                       void *stream);
+
 /* Client-side packing (host): CONV x [B][C][H][W] -> [B][cb][N]; DW is packed as
  * CONV with the plan's geometry; FC x [B][n_in] -> [B][in_ct][N]. */
 he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys);

@@ -385,7 +385,7 @@ he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes) 
 namespace he {
 size_t layer_ws_bytes(const Ctx &c, const Plan &p, uint32_t flags) { return ws_layout(c, p, flags).total; }
 he_status run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
-                    uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st);
+                    uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st, const uint64_t *seed = nullptr);
 }  // namespace he
 
 extern "C" {
@@ -397,23 +397,45 @@ he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in
   return run_layer(*ctx->c, plan->p, ct_in, plain, ct_out, flags, ws, ws_bytes, (hipStream_t)stream);
 }
 
+he_status he_corr_conv2d_seeded(he_ctx *ctx, const he_plan *plan, const uint64_t *ct0, const uint64_t *seed,
+                                const void *plain, uint64_t *ct_out, uint32_t flags, void *ws, size_t ws_bytes,
+                                void *stream) {
+  if (!ctx || !plan || !ct0 || !seed || !plain || !ct_out) return fail(HE_EINVAL, "null argument");
+  if (plan->ctx != ctx->c) return fail(HE_EINVAL, "plan belongs to another context");
+  if (flags & HE_IN_NTT) return fail(HE_EINVAL, "a seeded component is regenerated in coefficient form (no HE_IN_NTT)");
+  return run_layer(*ctx->c, plan->p, ct0, plain, ct_out, flags, ws, ws_bytes, (hipStream_t)stream, seed);
+}
+
+he_status he_expand_c1(he_ctx *ctx, const uint64_t *seed, uint32_t first_ct, uint32_t n_ct, uint64_t *out,
+                       void *stream) {
+  if (!ctx || !seed || (n_ct && !out)) return fail(HE_EINVAL, "null argument");
+  HIPCHK(launch_expand_c1(*ctx->c, out, seed[0], seed[1], first_ct, n_ct, (hipStream_t)stream), "expand c1");
+  return HE_OK;
+}
+
 }  // extern "C"
 
 he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
-                        uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st) {
+                        uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st, const uint64_t *seed) {
   const he_plan_info &in = p.info;
   const WsLayout L = ws_layout(c, p, flags);
   if (ws_bytes < L.total || (L.total && !ws)) return fail(HE_ENOMEM, "workspace too small");
   char *w = (char *)ws;
   if (flags & HE_VALIDATE) {
-    he_status s = validate(c, ct_in, (size_t)in.n_ct_in * 2 * c.L, w + L.flag, st);
+    // with a seed, ct_in holds component 0 only
+    he_status s = validate(c, ct_in, (size_t)in.n_ct_in * (seed ? 1 : 2) * c.L, w + L.flag, st);
     if (s != HE_OK) return s;
   }
   if ((flags & HE_PLAIN_POLY) == 0 && in.kind == HE_KIND_DW)
     return fail(HE_EUNSUPPORTED, "weight-gradient plaintexts are passed as packed polynomials (HE_PLAIN_POLY)");
   // 1. transform the input ciphertexts
   const uint64_t *ct_hat = ct_in;
-  if (!(flags & HE_IN_NTT)) {
+  if (seed) {
+    uint64_t *d = (uint64_t *)(w + L.ct_hat);
+    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd_seeded(c, c.s_fwd, d, ct_in, seed[0], seed[1], in.n_ct_in, st); }),
+           "conv fwd ct (seeded)");
+    ct_hat = d;
+  } else if (!(flags & HE_IN_NTT)) {
     uint64_t *d = (uint64_t *)(w + L.ct_hat);
     HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, st); }), "conv fwd ct");
     ct_hat = d;

@@ -81,6 +81,13 @@ hipError_t launch_ntt_fwd_lift(const Ctx &c, const Sched &s, uint64_t *out, cons
                                hipStream_t st);
 hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
                           hipStream_t st);
+// forward transform of n_ct ciphertexts [n_ct][2][L][N] whose component 0 is ct0
+// [n_ct][L][N] and whose component 1 is regenerated from the seed
+hipError_t launch_ntt_fwd_seeded(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct0, uint64_t seed0,
+                                 uint64_t seed1, uint32_t n_ct, hipStream_t st);
+// component 1 of ciphertexts first .. first+n_ct-1 -> out [n_ct][L][N]
+hipError_t launch_expand_c1(const Ctx &c, uint64_t *out, uint64_t seed0, uint64_t seed1, uint32_t first, uint32_t n_ct,
+                            hipStream_t st);
 // Term-list multiply-accumulate in the transformed domain followed by the
 // inverse transform (fused), or left transformed (out_ntt).  Output plane
 // (o, comp, i) = sum_t ct_hat[cti[t]][comp][i] * pt_hat[pti[t]][i].

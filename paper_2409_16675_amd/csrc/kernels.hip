@@ -5,6 +5,7 @@
 #include "he_internal.hpp"
 #include "ntt.hpp"
 #include "mac.hpp"
+#include "prng.hpp"
 
 namespace he {
 
@@ -36,6 +37,46 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
   auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
   ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+}
+
+// Forward transform of ciphertext planes whose component 1 is regenerated from
+// a seed: plane (j, comp, i) reads component 0 from ct0 [n][L][N] or forms
+// component 1 in registers (no HBM read of c1).
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd_seeded(
+    uint64_t *__restrict__ out, const uint64_t *__restrict__ ct0, const PrimeK *__restrict__ primes,
+    const typename A::Tw *__restrict__ tw, int L, Seed seed) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int plane = blockIdx.x;   // (j * 2 + comp) * L + i
+  const int i = plane % L;
+  const int comp = (plane / L) & 1;
+  const int j = plane / (2 * L);
+  const PrimeK pk = primes[i];
+  const A ar(pk);
+  uint64_t *dst = out + (size_t)plane * G::N;
+  const int tid = threadIdx.x;
+  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+  if (comp == 0) {
+    const uint64_t *src = ct0 + ((size_t)j * L + i) * G::N;
+    auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+    ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+  } else {
+    auto ld = [&](int k) { return ar.load(c1_residue(seed, (uint32_t)j, (uint32_t)i, (uint32_t)k, pk)); };
+    ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+  }
+}
+
+// Component 1 of ciphertexts first .. first+n-1 regenerated from the seed,
+// written [n][L][N] (coefficient form).
+__global__ void k_expand_c1(uint64_t *__restrict__ out, const PrimeK *__restrict__ primes, int L, int N, Seed seed,
+                            uint32_t first) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (uint32_t)N) return;
+  const uint32_t p = blockIdx.y;   // jj * L + i
+  const uint32_t i = p % (uint32_t)L, jj = p / (uint32_t)L;
+  out[(size_t)p * N + k] = c1_residue(seed, first + jj, i, k, primes[i]);
 }
 
 // Forward transform of signed integer polynomials lifted to every prime:
@@ -315,7 +356,7 @@ const TwU64 *tw_ptr<ArU64>(const Ctx &c, bool inverse) {
   return (const TwU64 *)(inverse ? c.d_tw_u64_inv : c.d_tw_u64_fwd);
 }
 
-enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV };
+enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED };
 
 struct LaunchArgs {
   uint64_t *out;
@@ -325,6 +366,7 @@ struct LaunchArgs {
   TermArgs ta;
   int accumulate;
   int ncomp;
+  Seed seed;
   unsigned grid;
 };
 
@@ -343,6 +385,11 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
       if ((e = prep(k_ntt_fwd_lift<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
       hipLaunchKernelGGL((k_ntt_fwd_lift<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.polys,
                          c.d_primes, tw_ptr<A>(c, false), (int)c.L);
+      break;
+    case OP_FWD_SEEDED:
+      if ((e = prep(k_ntt_fwd_seeded<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_fwd_seeded<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in,
+                         c.d_primes, tw_ptr<A>(c, false), (int)c.L, la.seed);
       break;
     case OP_INV:
       if ((e = prep(k_ntt_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
@@ -437,6 +484,25 @@ hipError_t launch_ntt_fwd(const Ctx &c, const Sched &s, uint64_t *out, const uin
   la.in = in;
   la.grid = n_planes;
   return dispatch(c, s, OP_FWD, la, st);
+}
+
+hipError_t launch_ntt_fwd_seeded(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct0, uint64_t seed0,
+                                 uint64_t seed1, uint32_t n_ct, hipStream_t st) {
+  LaunchArgs la{};
+  la.out = out;
+  la.in = ct0;
+  la.seed = Seed{seed0, seed1};
+  la.grid = n_ct * 2 * c.L;
+  return dispatch(c, s, OP_FWD_SEEDED, la, st);
+}
+
+hipError_t launch_expand_c1(const Ctx &c, uint64_t *out, uint64_t seed0, uint64_t seed1, uint32_t first, uint32_t n_ct,
+                            hipStream_t st) {
+  if (!n_ct) return hipSuccess;
+  dim3 grid((c.N + 255) / 256, n_ct * c.L);
+  hipLaunchKernelGGL(k_expand_c1, grid, dim3(256), 0, st, out, c.d_primes, (int)c.L, (int)c.N, Seed{seed0, seed1},
+                     first);
+  return hipGetLastError();
 }
 
 hipError_t launch_ntt_fwd_lift(const Ctx &c, const Sched &s, uint64_t *out, const int64_t *polys, uint32_t n_polys,

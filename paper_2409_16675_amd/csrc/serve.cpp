@@ -27,7 +27,7 @@
 namespace he {
 size_t layer_ws_bytes(const Ctx &c, const Plan &p, uint32_t flags);
 he_status run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
-                    uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st);
+                    uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st, const uint64_t *seed = nullptr);
 
 using Clock = std::chrono::steady_clock;
 static double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }

@@ -68,6 +68,9 @@ _SIGS = {
     "he_workspace_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
     "he_corr_conv2d": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
     "he_ppmul_ws_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
+    "he_corr_conv2d_seeded": [c_void_p, c_void_p, c_void_p, u64p, c_void_p, c_void_p, c_u32, c_void_p, c_size,
+                              c_void_p],
+    "he_expand_c1": [c_void_p, u64p, c_u32, c_u32, c_void_p, c_void_p],
     "he_ppmul": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
     "he_pack_input": [c_void_p, i32p, i64p],
     "he_extract_output": [c_void_p, i64p, i64p],
@@ -267,6 +270,23 @@ def he_workspace_size(plan, flags=0):
 def he_corr_conv2d(ctx, plan, ct_in, plain, ct_out, flags=0, ws=None, ws_bytes=0, stream=None):
     _chk(_lib.he_corr_conv2d(ctx, plan, _ptr(ct_in), _ptr(plain), _ptr(ct_out), flags, _ptr(ws), ws_bytes,
                              _stream(stream)), "he_corr_conv2d")
+
+
+def _seed(seed):
+    s = np.ascontiguousarray(np.array([int(seed[0]), int(seed[1])], dtype=np.uint64))
+    return s, s.ctypes.data_as(u64p)
+
+
+def he_corr_conv2d_seeded(ctx, plan, ct0, seed, plain, ct_out, flags=0, ws=None, ws_bytes=0, stream=None):
+    """he_corr_conv2d with input component 1 regenerated from `seed` (two 64-bit words); ct0 [n][L][N]."""
+    keep, ps = _seed(seed)
+    _chk(_lib.he_corr_conv2d_seeded(ctx, plan, _ptr(ct0), ps, _ptr(plain), _ptr(ct_out), flags, _ptr(ws), ws_bytes,
+                                    _stream(stream)), "he_corr_conv2d_seeded")
+
+
+def he_expand_c1(ctx, seed, first_ct, n_ct, out, stream=None):
+    keep, ps = _seed(seed)
+    _chk(_lib.he_expand_c1(ctx, ps, first_ct, n_ct, _ptr(out), _stream(stream)), "he_expand_c1")
 
 
 def he_ppmul_ws_size(plan, flags=0):
