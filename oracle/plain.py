@@ -37,6 +37,26 @@ def conv2d_weight_grad(x, dy, P, h):
     return dw
 
 
+def conv2d_input_grad(dy, w, P, H, W):
+    """Input gradient of conv2d (Section 2, training): dX[c, y, z] = sum over m, a, b
+    of dy[m, y + P - a, z + P - b] * w[m, c, a, b] where that dy index lies in the
+    output map; dy[M, Ho, Wo], w[M, C, h, h] -> dX[C, H, W] (stride 1)."""
+    M, Ho, Wo = dy.shape
+    _, C, h, _ = w.shape
+    dx = np.zeros((C, H, W), dtype=np.int64)
+    for a in range(h):
+        for b in range(h):
+            for y in range(H):
+                yy = y + P - a
+                if not 0 <= yy < Ho:
+                    continue
+                for z in range(W):
+                    zz = z + P - b
+                    if 0 <= zz < Wo:
+                        dx[:, y, z] += w[:, :, a, b].astype(np.int64).T @ dy[:, yy, zz].astype(np.int64)
+    return dx
+
+
 def matvec(Wm, x):
     return Wm.astype(np.int64) @ x.astype(np.int64)
 
