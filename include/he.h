@@ -152,13 +152,20 @@ he_status he_cpmul_acc_ws(const he_ctx *ctx, uint32_t K, uint32_t flags, size_t 
 #define HE_KIND_DW 1     /* weight gradient (CryptoTrain-P terms):
                             out[m][k] = sum_b [X_b,k] (x) (dY_b,m - r) + [dY_b,m] (x) (X_b,k - r) */
 #define HE_KIND_FC 2     /* fully connected: out[b][o] = sum_j ct_in[b][j] (x) W[o][j] */
+#define HE_KIND_DX 3     /* input gradient of a conv layer (Section 2, training):
+                            dX[b][c] = sum_m [dY_b,m] (x) rot180(W[m][c]) with padding h-1-P,
+                            i.e. the forward conv of dY with the kernel transposed in its
+                            channels and rotated by 180 degrees; the shape fields are the
+                            forward layer's (C, M, H, W, h, P), the input is dY
+                            [B][M][H_out][W_out], the weights the forward W [M][C][h][h],
+                            the output dX [B][C][H][W] */
 
 typedef struct {
   int32_t kind;          /* HE_KIND_* */
   uint32_t B;            /* batch */
-  uint32_t C, M;         /* input / output channels (CONV, DW) */
-  uint32_t H, W;         /* input map (CONV, DW) */
-  uint32_t h;            /* kernel side (CONV, DW: the forward kernel) */
+  uint32_t C, M;         /* input / output channels (CONV, DW; DX: of the forward layer) */
+  uint32_t H, W;         /* input map (CONV, DW; DX: of the forward layer) */
+  uint32_t h;            /* kernel side (CONV, DW, DX: the forward kernel) */
   uint32_t P;            /* zero padding, stride 1 */
   uint32_t n_in, n_out;  /* FC sizes */
 } he_conv_shape;
@@ -173,9 +180,9 @@ typedef struct {
   uint32_t cb;           /* channel blocks, ceil(C / Cw) */
   uint32_t Hout, Wout;   /* conv output map */
   uint32_t n_iw, n_ow;   /* FC: input chunk width, outputs per polynomial */
-  uint32_t n_ct_in;      /* ciphertexts read  (CONV: B*cb; DW: B*(cb+M); FC: B*in_ct) */
-  uint32_t n_pt;         /* plaintext polynomials (CONV: M*cb; DW: B*(M+cb); FC: out_ct*in_ct) */
-  uint32_t n_ct_out;     /* ciphertexts written (CONV: B*M; DW: M*cb; FC: B*out_ct) */
+  uint32_t n_ct_in;      /* ciphertexts read  (CONV: B*cb; DW: B*(cb+M); FC: B*in_ct; DX: B*cb over M) */
+  uint32_t n_pt;         /* plaintext polynomials (CONV: M*cb; DW: B*(M+cb); FC: out_ct*in_ct; DX: C*cb) */
+  uint32_t n_ct_out;     /* ciphertexts written (CONV: B*M; DW: M*cb; FC: B*out_ct; DX: B*C) */
   uint32_t n_terms;      /* CPMul count */
 } he_plan_info;
 

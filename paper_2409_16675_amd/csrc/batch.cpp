@@ -89,11 +89,12 @@ static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
   pj.logN = c.logN;
   pj.L = c.L;
   pj.accumulate = (f & HE_ACCUMULATE) ? 1u : 0u;
-  pj.pkind = (f & HE_PLAIN_POLY) ? PK_POLY : (in.kind == HE_KIND_FC ? PK_FC : PK_CONV);
+  pj.pkind = (f & HE_PLAIN_POLY) ? PK_POLY
+                                 : (in.kind == HE_KIND_FC ? PK_FC : (in.kind == HE_KIND_DX ? PK_CONV_DX : PK_CONV));
   if (in.kind == HE_KIND_DW && pj.pkind != PK_POLY) return fail(HE_EUNSUPPORTED, "weight-gradient jobs need HE_PLAIN_POLY");
-  pj.M = p.shape.M;
-  pj.C = p.shape.C;
-  pj.h = p.shape.h;
+  pj.M = p.eq.M;
+  pj.C = p.eq.C;
+  pj.h = p.eq.h;
   pj.O = in.O;
   pj.S = in.S;
   pj.Cw = in.Cw;

@@ -5,7 +5,7 @@
 namespace he {
 
 enum PTaskKind : uint32_t { PT_FWD_CT = 0, PT_PT = 1, PT_MAC_INV = 2 };
-enum PlainKind : uint32_t { PK_CONV = 0, PK_FC = 1, PK_POLY = 2 };
+enum PlainKind : uint32_t { PK_CONV = 0, PK_FC = 1, PK_POLY = 2, PK_CONV_DX = 3 };
 
 // control words: pre-task queue head, error flag, one head per XCD queue of
 // dependent tasks (each on its own 128-byte line), then one completion counter

@@ -447,9 +447,9 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
     HIPCHK(timed(c, st, KK_PACK, [&] {
              hipError_t e = launch_zero_i64(pp, (size_t)in.n_pt * c.N, st);
              if (e != hipSuccess) return e;
-             if (in.kind == HE_KIND_CONV)
-               return launch_pack_conv_w(pp, (const int32_t *)plain, p.shape.M, p.shape.C, p.shape.h, in.O, in.S,
-                                         in.Cw, in.cb, c.N, st);
+             if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX)
+               return launch_pack_conv_w(pp, (const int32_t *)plain, p.eq.M, p.eq.C, p.eq.h, in.O, in.S, in.Cw,
+                                         in.cb, c.N, in.kind == HE_KIND_DX, st);
              return launch_pack_fc_w(pp, (const int32_t *)plain, p.shape.n_out, p.shape.n_in, in.n_iw, in.n_ow,
                                      (p.shape.n_in + in.n_iw - 1) / in.n_iw, c.N, st);
            }),
@@ -488,7 +488,7 @@ he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys) {
   if (!plan || !x || !polys) return fail(HE_EINVAL, "null argument");
   const Plan &p = plan->p;
   const he_plan_info &in = p.info;
-  const he_conv_shape &s = p.shape;
+  const he_conv_shape &s = p.eq;   // DX: dY packed as the input of the equivalent conv
   const uint32_t N = in.N;
   if (s.kind == HE_KIND_FC) {
     const uint32_t ict = (s.n_in + in.n_iw - 1) / in.n_iw;
@@ -512,7 +512,7 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
   if (!plan || !polys || !y) return fail(HE_EINVAL, "null argument");
   const Plan &p = plan->p;
   const he_plan_info &in = p.info;
-  const he_conv_shape &s = p.shape;
+  const he_conv_shape &s = p.eq;   // DX: dX is the output of the equivalent conv
   const uint32_t N = in.N;
   if (s.kind == HE_KIND_FC) {
     const uint32_t oct = (s.n_out + in.n_ow - 1) / in.n_ow;

@@ -103,8 +103,10 @@ hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_
                       const Terms &tm, bool accumulate, bool out_ntt, hipStream_t st, int ncomp = 2);
 
 hipError_t launch_zero_i64(int64_t *p, size_t n, hipStream_t st);
+// dx: read the kernel of an input gradient from forward weights [C][M][h][h]
+// (transposed channels, rotated by 180 degrees)
 hipError_t launch_pack_conv_w(int64_t *polys, const int32_t *w, uint32_t M, uint32_t C, uint32_t h, uint32_t O,
-                              uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, hipStream_t st);
+                              uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, bool dx, hipStream_t st);
 hipError_t launch_pack_fc_w(int64_t *polys, const int32_t *W, uint32_t n_out, uint32_t n_in, uint32_t n_iw,
                             uint32_t n_ow, uint32_t in_ct, uint32_t N, hipStream_t st);
 // validation: count of coefficients >= q_i in [n][L][N] planes, written to *bad (device)

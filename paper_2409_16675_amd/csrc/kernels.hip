@@ -224,15 +224,18 @@ __global__ void k_zero_i64(int64_t *p, size_t n) {
 // Weights w[M][C][h][h] -> polynomials [M][cb][N]: channel c of block c / Cw at
 // offset -(c mod Cw) * S (stored at N - cc*S + p with the sign flipped, X^N = -1),
 // within a channel w[a][b] at (h-1-a)*O + (h-1-b)  (pi_w, Eq. 2).
+// dx: the kernel of an input gradient, w'[m][c][a][b] = w[c][m][h-1-a][h-1-b]
+// read from the forward weights w [C][M][h][h] (M, C: the equivalent conv's).
 __global__ void k_pack_conv_w(int64_t *__restrict__ polys, const int32_t *__restrict__ w, uint32_t M, uint32_t C,
-                              uint32_t h, uint32_t O, uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N) {
+                              uint32_t h, uint32_t O, uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, int dx) {
   const size_t total = (size_t)M * C * h * h;
   for (size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
     const uint32_t b = id % h, a = (id / h) % h, c = (id / ((size_t)h * h)) % C, m = id / ((size_t)h * h * C);
     const uint32_t blk = c / Cw, cc = c % Cw;
     const uint32_t p = (h - 1 - a) * O + (h - 1 - b);
     int64_t *poly = polys + ((size_t)m * cb + blk) * N;
-    const int64_t v = w[id];
+    const size_t src = dx ? (((size_t)c * M + m) * h + (h - 1 - a)) * h + (h - 1 - b) : id;
+    const int64_t v = w[src];
     if (cc == 0) poly[p] = v;
     else poly[N - cc * S + p] = -v;
   }
@@ -558,10 +561,11 @@ hipError_t launch_zero_i64(int64_t *p, size_t n, hipStream_t st) {
 }
 
 hipError_t launch_pack_conv_w(int64_t *polys, const int32_t *w, uint32_t M, uint32_t C, uint32_t h, uint32_t O,
-                              uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, hipStream_t st) {
+                              uint32_t S, uint32_t Cw, uint32_t cb, uint32_t N, bool dx, hipStream_t st) {
   const size_t total = (size_t)M * C * h * h;
   if (!total) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_conv_w, dim3(grid_for(total, 256)), dim3(256), 0, st, polys, w, M, C, h, O, S, Cw, cb, N);
+  hipLaunchKernelGGL(k_pack_conv_w, dim3(grid_for(total, 256)), dim3(256), 0, st, polys, w, M, C, h, O, S, Cw, cb, N,
+                     dx ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -75,13 +75,17 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       __syncthreads();
       const HE_GLOBAL int32_t *w = as_global((const int32_t *)jb.plain);
       if (valid) {
-        if (jb.pkind == PK_CONV) {
+        if (jb.pkind == PK_CONV || jb.pkind == PK_CONV_DX) {
           const uint32_t m = pp / jb.cb, blk = pp % jb.cb, hh = jb.h * jb.h;
           const uint32_t c0 = blk * jb.Cw, c1 = min(jb.C, c0 + jb.Cw);
           const uint32_t n = (c1 - c0) * hh;
+          const bool dx = jb.pkind == PK_CONV_DX;
           for (uint32_t id = tid_g; id < n; id += G::NT) {
             const uint32_t cc = id / hh, ab = id % hh, a = ab / jb.h, b = ab % jb.h;
-            const int64_t v = w[((size_t)m * jb.C + c0 + cc) * hh + ab];
+            // input gradient: forward weights [C][M][h][h], transposed and rotated
+            const size_t src = dx ? (((size_t)(c0 + cc) * jb.M + m) * jb.h + (jb.h - 1 - a)) * jb.h + (jb.h - 1 - b)
+                                  : ((size_t)m * jb.C + c0 + cc) * hh + ab;
+            const int64_t v = w[src];
             const uint32_t pos = (jb.h - 1 - a) * jb.O + (jb.h - 1 - b);
             if (cc == 0) lds_g[lpad(pos)] = ar.load_signed(v);
             else lds_g[lpad(G::N - cc * jb.S + pos)] = ar.load_signed(-v);

@@ -8,7 +8,35 @@ namespace he {
 
 static uint32_t cdiv(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
+static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p);
+
+// An input gradient (Section 2: dX = conv(w, dY) with padding) is planned as the
+// forward conv of dY [B][M][H_out][W_out] with the kernel transposed in its
+// channels and rotated by 180 degrees, padding h-1-P: its output map is H x W.
 he_status make_plan(const Ctx &c, const he_conv_shape &s, Plan &p) {
+  if (s.kind != HE_KIND_DX) {
+    p.eq = s;
+    return make_plan_geom(c, s, p);
+  }
+  if (!s.C || !s.M || !s.H || !s.W || !s.h || !s.B) return fail(HE_EINVAL, "conv sizes must be positive");
+  if (s.P >= s.h) return fail(HE_EINVAL, "padding must be smaller than the kernel");
+  if (s.H + 2 * s.P < s.h || s.W + 2 * s.P < s.h) return fail(HE_EINVAL, "kernel larger than padded input");
+  he_conv_shape e = s;
+  e.kind = HE_KIND_CONV;
+  e.C = s.M;
+  e.M = s.C;
+  e.H = s.H + 2 * s.P - s.h + 1;
+  e.W = s.W + 2 * s.P - s.h + 1;
+  e.P = s.h - 1 - s.P;
+  he_status st = make_plan_geom(c, e, p);
+  if (st != HE_OK) return st;
+  p.shape = s;
+  p.eq = e;
+  p.info.kind = HE_KIND_DX;
+  return HE_OK;
+}
+
+static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p) {
   p.shape = s;
   he_plan_info &in = p.info;
   in = he_plan_info{};

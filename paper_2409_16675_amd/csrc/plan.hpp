@@ -8,6 +8,10 @@ namespace he {
 
 struct Plan {
   he_conv_shape shape{};
+  // geometry the packing follows: the shape itself, or for an input gradient
+  // (DX) the equivalent forward conv of dY (channels M -> C, map H_out x W_out,
+  // padding h-1-P)
+  he_conv_shape eq{};
   he_plan_info info{};
   uint32_t hk = 0;                        // polynomial-kernel side (h for CONV, Hout for DW)
   std::vector<int32_t> row, cti, pti;     // term lists (host)

@@ -23,7 +23,7 @@ HE_OK = 0
 HE_EINVAL, HE_EUNSUPPORTED, HE_ENOMEM, HE_EDEVICE, HE_ERANGE, HE_EBUSY, HE_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 HE_ARITH_AUTO, HE_ARITH_F64, HE_ARITH_U64 = 0, 1, 2
 HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
-HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC = 0, 1, 2
+HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC, HE_KIND_DX = 0, 1, 2, 3
 
 c_void_p, c_u32, c_u64, c_i32, c_size = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
 u64p = ctypes.POINTER(ctypes.c_uint64)

@@ -167,3 +167,45 @@ def test_fc_parity_and_decrypt(gpu_lib, N, L, B, n_in, n_out):
     dec = np.stack([bfv.decrypt(got[o], s, ctx.q, ctx.psi, T) for o in range(got.shape[0])])
     y = he.he_extract_output(plan.h, dec, B * n_out).reshape(B, n_out)
     assert np.array_equal(y, plain.mod_t(np.stack([plain.matvec(Wm, x[b]) for b in range(B)]), T))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,B,C,M,H,h,P", [(1024, 2, 2, 3, 2, 6, 3, 1), (4096, 2, 2, 16, 8, 16, 3, 1),
+                                             (2048, 2, 1, 4, 3, 7, 5, 2)])
+def test_input_gradient_parity_and_decrypt(gpu_lib, N, L, B, C, M, H, h, P):
+    # dX = conv(w, dY) with padding (Section 2, training) as the forward conv of dY
+    # with the kernel transposed and rotated: bit-exact against the oracle's ring
+    # products, decrypting to the plaintext input gradient mod t
+    he = gpu_lib
+    ctx = he.Context(N, L)
+    plan = he.Plan(ctx, he.HE_KIND_DX, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    info = plan.info
+    Ho = H + 2 * P - h + 1
+    assert (info["Hout"], info["Wout"]) == (H, H)
+    geo = packing.ConvGeometry(M, Ho, Ho, h, h - 1 - P, N)
+    dy = synth.int8_uniform(synth.rng(80, synth.STREAM_ACT, N), (B, M, Ho, Ho))
+    w = synth.int8_uniform(synth.rng(80, synth.STREAM_PT, N), (M, C, h, h))
+    polys = he.he_pack_input(plan.h, dy.reshape(-1), B * info["cb"] * N).reshape(B, info["cb"], N)
+    assert np.array_equal(polys, np.stack([packing.pack_conv_input(dy[b], geo) for b in range(B)]))
+    ct, s = encrypt_polys(ctx, polys, 80)
+    w_eq = np.ascontiguousarray(np.transpose(w, (1, 0, 2, 3))[:, :, ::-1, ::-1])
+    pt = core.lift(packing.pack_conv_weight(w_eq, geo).reshape(-1, N), ctx.q)
+    row, cti, pti = packing.conv_terms(B, C, geo.cb)
+    expect = core.csr_cpmul(ct, pt, row, cti, pti, ctx.q, ctx.psi, method=2)
+    d_w = torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda()
+    got = run_layer(he, ctx, plan, ct, d_w)
+    assert_equal_u64(got, expect, "input gradient")
+    # the same job inside a persistent batch
+    out_b = he.empty_u64(tuple(got.shape))
+    d_ct = he.to_device_u64(ct)
+    bt = he.he_batch_create(0)
+    he.he_batch_add(bt, ctx.h, plan.h, d_ct, d_w, out_b, 0)
+    he.he_batch_build(bt)
+    he.he_batch_run(bt)
+    he.he_batch_sync(bt)
+    assert_equal_u64(he.to_numpy_u64(out_b), expect, "input gradient, batched")
+    he.he_batch_destroy(bt)
+    dec = np.stack([bfv.decrypt(got[o], s, ctx.q, ctx.psi, T) for o in range(got.shape[0])])
+    dx = he.he_extract_output(plan.h, dec, B * C * H * H).reshape(B, C, H, H)
+    for b in range(B):
+        assert np.array_equal(dx[b], plain.mod_t(plain.conv2d_input_grad(dy[b], w, P, H, H), T)), b
