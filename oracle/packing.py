@@ -237,3 +237,112 @@ def ceil_div(a, b):
 
 
 __all__ = [n for n in dir() if not n.startswith("_") and n not in ("math", "np")]
+
+
+# ------------------------------------------------------------ spatial windows
+# Section 3.3 splits an input whose single channel does not fit one ring element
+# into windows H_w x W_w; its objective is garbled.  Reading: disjoint tiles of
+# the unpadded input, tile (r, s) covering rows r*H_w.. and columns s*W_w.., each
+# packed with pitch O_w = max(W_w, H_w) + h - 1 and multiplied by the same kernel
+# polynomials; the product of a tile holds that tile's full correlation
+# F_t[u, v] (u < H_w + h - 1, v < W_w + h - 1) at u*O_w + v, which the client
+# adds into F at offset (r*H_w, s*W_w) (overlap-add: F is linear in x) and then
+# crops by P.  The window is the one minimising the CPMul count
+# ceil(H/H_w) * ceil(W/W_w) * cb * M subject to span_w + 1 <= N; ties go to fewer
+# input ciphertexts, then larger H_w, then larger W_w.  Without a need to split
+# (the whole map fits) the single-tile geometry is the plain one.
+
+
+class WindowGeometry:
+    """Tiles of a conv whose input map is split into windows."""
+
+    def __init__(self, C, M, H, W, h, P, N):
+        self.C, self.M, self.H, self.W, self.h, self.P, self.N = C, M, H, W, h, P, N
+        self.Hout = H + 2 * P - h + 1
+        self.Wout = W + 2 * P - h + 1
+        try:
+            g = ConvGeometry(C, H, W, h, P, N)
+            self.Hw, self.Ww = H, W
+        except ValueError:
+            best = None
+            for hw in range(1, H + 1):
+                for ww in range(1, W + 1):
+                    O = max(ww, hw) + h - 1
+                    S = (hw + h - 2) * O + (ww + h - 2) + 1
+                    if S > N:
+                        continue
+                    cb = -(-C // (N // S))
+                    tiles = -(-H // hw) * -(-W // ww)
+                    key = (tiles * cb * M, tiles * cb, -hw, -ww)
+                    if best is None or key < best[0]:
+                        best = (key, hw, ww)
+            if best is None:
+                raise ValueError("no window fits one polynomial")
+            self.Hw, self.Ww = best[1], best[2]
+        self.O = max(self.Ww, self.Hw) + h - 1
+        self.span = (self.Hw + h - 2) * self.O + (self.Ww + h - 2)
+        self.S = self.span + 1
+        self.Cw = N // self.S
+        self.cb = -(-C // self.Cw)
+        self.th = -(-H // self.Hw)
+        self.tw = -(-W // self.Ww)
+        self.tiles = self.th * self.tw
+
+    def tile_input(self, x, t):
+        """The [C, Hw, Ww] zero-extended sub-image of tile t (row-major over tiles)."""
+        r, s = divmod(t, self.tw)
+        sub = np.zeros((self.C, self.Hw, self.Ww), dtype=np.int64)
+        blk = x[:, r * self.Hw:(r + 1) * self.Hw, s * self.Ww:(s + 1) * self.Ww]
+        sub[:, :blk.shape[1], :blk.shape[2]] = blk
+        return sub
+
+    def pack_input(self, x):
+        """x[C, H, W] -> [tiles, cb, N]."""
+        out = np.zeros((self.tiles, self.cb, self.N), dtype=np.int64)
+        for t in range(self.tiles):
+            sub = self.tile_input(x, t)
+            for c in range(self.C):
+                k, cc = divmod(c, self.Cw)
+                for i in range(self.Hw):
+                    out[t, k, cc * self.S + i * self.O:cc * self.S + i * self.O + self.Ww] += sub[c, i]
+        return out
+
+    def pack_weight(self, w):
+        """w[M, C, h, h] -> [M, cb, N] (pitch O, channel offsets -cc*S, negated)."""
+        out = np.zeros((self.M, self.cb, self.N), dtype=np.int64)
+        h = self.h
+        for m in range(self.M):
+            for c in range(self.C):
+                k, cc = divmod(c, self.Cw)
+                for a in range(h):
+                    for b in range(h):
+                        p = (h - 1 - a) * self.O + (h - 1 - b)
+                        if cc == 0:
+                            out[m, k, p] += w[m, c, a, b]
+                        else:
+                            out[m, k, self.N - cc * self.S + p] -= w[m, c, a, b]
+        return out
+
+    def terms(self, B):
+        """Output (b, t, m) = sum_k ct[b, t, k] (x) pt[m, k]."""
+        row, cti, pti = [0], [], []
+        for b in range(B):
+            for t in range(self.tiles):
+                for m in range(self.M):
+                    for k in range(self.cb):
+                        cti.append((b * self.tiles + t) * self.cb + k)
+                        pti.append(m * self.cb + k)
+                    row.append(len(cti))
+        return np.array(row, np.int32), np.array(cti, np.int32), np.array(pti, np.int32)
+
+    def extract(self, polys):
+        """Products [tiles, N] of one (b, m) -> out[Hout, Wout] by overlap-add, then crop by P."""
+        h = self.h
+        F = np.zeros((self.th * self.Hw + h - 1, self.tw * self.Ww + h - 1), dtype=np.int64)
+        for t in range(self.tiles):
+            r, s = divmod(t, self.tw)
+            for u in range(self.Hw + h - 1):
+                F[r * self.Hw + u, s * self.Ww:s * self.Ww + self.Ww + h - 1] += \
+                    polys[t][u * self.O:u * self.O + self.Ww + h - 1]
+        off = h - 1 - self.P
+        return F[off:off + self.Hout, off:off + self.Wout]
