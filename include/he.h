@@ -184,11 +184,19 @@ typedef struct {
   uint32_t n_pt;         /* plaintext polynomials (CONV: M*cb; DW: B*(M+cb); FC: out_ct*in_ct; DX: C*cb) */
   uint32_t n_ct_out;     /* ciphertexts written (CONV: B*M; DW: M*cb; FC: B*out_ct; DX: B*C) */
   uint32_t n_terms;      /* CPMul count */
+  uint32_t Hw, Ww;       /* CONV, DX: input window (the whole map unless it does not fit one polynomial) */
+  uint32_t tiles;        /* CONV, DX: windows per input map; inputs and outputs are per (b, tile): the
+                            counts above are then B*tiles*cb and B*tiles*M (DX: B*tiles*C) */
 } he_plan_info;
 
 /* Plan a layer on a context.  Allocates host memory and a small device copy of
- * the term lists on the context's device.  Returns
- * HE_EUNSUPPORTED when one channel does not fit one polynomial. */
+ * the term lists on the context's device.  A CONV or DX map whose single
+ * channel does not fit one polynomial is split into windows (Section 3.3):
+ * disjoint H_w x W_w tiles of the unpadded input with pitch
+ * O = max(W_w, H_w) + h - 1, chosen to minimise the CPMul count (ties: fewer
+ * input ciphertexts, then larger H_w, then larger W_w); he_extract_output
+ * overlap-adds the tiles' products.  HE_EUNSUPPORTED when no window fits, or
+ * when a weight-gradient (DW) channel does not fit. */
 he_status he_plan_create(const he_ctx *ctx, const he_conv_shape *shape, he_plan **out);
 he_status he_plan_destroy(he_plan *plan);
 he_status he_plan_get_info(const he_plan *plan, he_plan_info *info);
@@ -227,10 +235,12 @@ he_status he_corr_conv2d_seeded(he_ctx *ctx, const he_plan *plan, const uint64_t
 he_status he_expand_c1(he_ctx *ctx, const uint64_t *seed, uint32_t first_ct, uint32_t n_ct, uint64_t *out,
                        void *stream);
 
-/* Client-side packing (host): CONV x [B][C][H][W] -> [B][cb][N]; DW is packed as
+/* Client-side packing (host): CONV x [B][C][H][W] -> [B][tiles][cb][N]; DW is packed as
  * CONV with the plan's geometry; FC x [B][n_in] -> [B][in_ct][N]. */
 he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys);
-/* Client-side extraction (host): CONV [B][M][N] -> y [B][M][Hout][Wout];
+/* Client-side extraction (host): CONV [B][tiles][M][N] -> y [B][M][Hout][Wout]
+ * (windowed plans: the tiles' coefficients summed, so values are sums of the
+ * given residues -- reduce mod t after extraction);
  * FC [B][out_ct][N] -> y [B][n_out]; DW [M][cb][N] -> dW [M][C][Hk][Hk] with
  * Hk = H + 2P - Hout + 1.  Values are taken as given (mod t after decryption). */
 he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *y);

@@ -498,12 +498,19 @@ he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys) {
         polys[((size_t)b * ict + j / in.n_iw) * N + j % in.n_iw] = x[(size_t)b * s.n_in + j];
     return HE_OK;
   }
-  std::memset(polys, 0, sizeof(int64_t) * (size_t)s.B * in.cb * N);
+  // CONV, DX and DW inputs: per (image, window) cb polynomials; a window covers
+  // rows r*Hw.. and columns s*Ww.. of the map (the whole map when unsplit)
+  const uint32_t T = in.tiles ? in.tiles : 1, tw = (s.W + in.Ww - 1) / in.Ww;
+  std::memset(polys, 0, sizeof(int64_t) * (size_t)s.B * T * in.cb * N);
   for (uint32_t b = 0; b < s.B; ++b)
-    for (uint32_t c = 0; c < s.C; ++c) {
-      int64_t *poly = polys + ((size_t)b * in.cb + c / in.Cw) * N + (size_t)(c % in.Cw) * in.S;
-      for (uint32_t i = 0; i < s.H; ++i)
-        for (uint32_t j = 0; j < s.W; ++j) poly[i * in.O + j] = x[(((size_t)b * s.C + c) * s.H + i) * s.W + j];
+    for (uint32_t t = 0; t < T; ++t) {
+      const uint32_t r0 = (t / tw) * in.Hw, c0 = (t % tw) * in.Ww;
+      for (uint32_t c = 0; c < s.C; ++c) {
+        int64_t *poly = polys + (((size_t)b * T + t) * in.cb + c / in.Cw) * N + (size_t)(c % in.Cw) * in.S;
+        for (uint32_t i = 0; i < in.Hw && r0 + i < s.H; ++i)
+          for (uint32_t j = 0; j < in.Ww && c0 + j < s.W; ++j)
+            poly[i * in.O + j] = x[(((size_t)b * s.C + c) * s.H + r0 + i) * s.W + c0 + j];
+      }
     }
   return HE_OK;
 }
@@ -522,13 +529,34 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
     return HE_OK;
   }
   if (s.kind == HE_KIND_CONV) {
+    const uint32_t T = in.tiles ? in.tiles : 1, tw = (s.W + in.Ww - 1) / in.Ww, th = T / tw, h = s.h;
+    if (T == 1) {
+      for (uint32_t b = 0; b < s.B; ++b)
+        for (uint32_t m = 0; m < s.M; ++m) {
+          const int64_t *poly = polys + ((size_t)b * s.M + m) * N;
+          for (uint32_t yy = 0; yy < in.Hout; ++yy)
+            for (uint32_t zz = 0; zz < in.Wout; ++zz)
+              y[(((size_t)b * s.M + m) * in.Hout + yy) * in.Wout + zz] =
+                  poly[(yy + h - 1 - s.P) * in.O + (zz + h - 1 - s.P)];
+        }
+      return HE_OK;
+    }
+    // windows: overlap-add each tile's full correlation at (r*Hw, s*Ww), then crop
+    const uint32_t FH = th * in.Hw + h - 1, FW = tw * in.Ww + h - 1;
+    std::vector<int64_t> F((size_t)FH * FW);
     for (uint32_t b = 0; b < s.B; ++b)
       for (uint32_t m = 0; m < s.M; ++m) {
-        const int64_t *poly = polys + ((size_t)b * s.M + m) * N;
+        std::fill(F.begin(), F.end(), 0);
+        for (uint32_t t = 0; t < T; ++t) {
+          const int64_t *poly = polys + (((size_t)b * T + t) * s.M + m) * N;
+          const uint32_t r0 = (t / tw) * in.Hw, c0 = (t % tw) * in.Ww;
+          for (uint32_t u = 0; u < in.Hw + h - 1; ++u)
+            for (uint32_t v = 0; v < in.Ww + h - 1; ++v) F[(size_t)(r0 + u) * FW + c0 + v] += poly[u * in.O + v];
+        }
         for (uint32_t yy = 0; yy < in.Hout; ++yy)
           for (uint32_t zz = 0; zz < in.Wout; ++zz)
             y[(((size_t)b * s.M + m) * in.Hout + yy) * in.Wout + zz] =
-                poly[(yy + s.h - 1 - s.P) * in.O + (zz + s.h - 1 - s.P)];
+                F[(size_t)(yy + h - 1 - s.P) * FW + (zz + h - 1 - s.P)];
       }
     return HE_OK;
   }

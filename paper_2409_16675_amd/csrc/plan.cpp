@@ -60,25 +60,52 @@ static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p) {
       hk = in.Hout;
     }
     p.hk = hk;
+    in.Hw = s.H;
+    in.Ww = s.W;
     in.O = std::max(s.W, s.H) + hk - 1;
     in.span = (s.H + hk - 2) * in.O + (s.W + hk - 2);
+    if (in.span + 1 > N) {
+      // spatial windows (Section 3.3, garbled objective; reading): disjoint
+      // tiles, the cheapest in CPMul count that fit, ties to fewer input
+      // ciphertexts, then larger H_w, then larger W_w
+      if (s.kind != HE_KIND_CONV) return fail(HE_EUNSUPPORTED, "weight-gradient channel does not fit one polynomial");
+      uint64_t best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+      for (uint32_t hw = 1; hw <= s.H; ++hw)
+        for (uint32_t ww = 1; ww <= s.W; ++ww) {
+          const uint64_t O = std::max(ww, hw) + hk - 1;
+          const uint64_t S = (hw + hk - 2) * O + (ww + hk - 2) + 1;
+          if (S > N) continue;
+          const uint64_t cb = cdiv(s.C, (uint32_t)(N / S)), tiles = (uint64_t)cdiv(s.H, hw) * cdiv(s.W, ww);
+          const uint64_t key[4] = {tiles * cb * s.M, tiles * cb, (uint64_t)(s.H - hw), (uint64_t)(s.W - ww)};
+          if (std::lexicographical_compare(key, key + 4, best, best + 4)) {
+            std::copy(key, key + 4, best);
+            in.Hw = hw;
+            in.Ww = ww;
+          }
+        }
+      if (best[0] == ~0ull) return fail(HE_EUNSUPPORTED, "no input window fits one polynomial");
+      in.O = std::max(in.Ww, in.Hw) + hk - 1;
+      in.span = (in.Hw + hk - 2) * in.O + (in.Ww + hk - 2);
+    }
     in.S = in.span + 1;
-    if (in.S > N) return fail(HE_EUNSUPPORTED, "one channel does not fit one polynomial (needs spatial windows)");
     in.Cw = N / in.S;
     in.cb = cdiv(s.C, in.Cw);
+    in.tiles = cdiv(s.H, in.Hw) * cdiv(s.W, in.Ww);
     if (s.kind == HE_KIND_CONV) {
-      in.n_ct_in = s.B * in.cb;
+      const uint32_t T = in.tiles;
+      in.n_ct_in = s.B * T * in.cb;
       in.n_pt = s.M * in.cb;
-      in.n_ct_out = s.B * s.M;
+      in.n_ct_out = s.B * T * s.M;
       p.row.push_back(0);
       for (uint32_t b = 0; b < s.B; ++b)
-        for (uint32_t m = 0; m < s.M; ++m) {
-          for (uint32_t k = 0; k < in.cb; ++k) {
-            p.cti.push_back((int32_t)(b * in.cb + k));
-            p.pti.push_back((int32_t)(m * in.cb + k));
+        for (uint32_t t = 0; t < T; ++t)
+          for (uint32_t m = 0; m < s.M; ++m) {
+            for (uint32_t k = 0; k < in.cb; ++k) {
+              p.cti.push_back((int32_t)((b * T + t) * in.cb + k));
+              p.pti.push_back((int32_t)(m * in.cb + k));
+            }
+            p.row.push_back((int32_t)p.cti.size());
           }
-          p.row.push_back((int32_t)p.cti.size());
-        }
     } else {
       // ct [B][cb + M] = ([X_b,k] blocks, [dY_b,m]); pt [B][M + cb] = ((dY-r)_b,m, (X-r)_b,k); out [M][cb]
       const uint32_t cb = in.cb, M = s.M;

@@ -44,7 +44,7 @@ class he_conv_shape(ctypes.Structure):
 class he_plan_info(ctypes.Structure):
     _fields_ = [(n, c_i32 if n == "kind" else c_u32) for n in
                 ("kind", "N", "O", "span", "S", "Cw", "cb", "Hout", "Wout", "n_iw", "n_ow", "n_ct_in", "n_pt",
-                 "n_ct_out", "n_terms")]
+                 "n_ct_out", "n_terms", "Hw", "Ww", "tiles")]
 
 
 _SIGS = {

@@ -209,3 +209,51 @@ def test_input_gradient_parity_and_decrypt(gpu_lib, N, L, B, C, M, H, h, P):
     dx = he.he_extract_output(plan.h, dec, B * C * H * H).reshape(B, C, H, H)
     for b in range(B):
         assert np.array_equal(dx[b], plain.mod_t(plain.conv2d_input_grad(dy[b], w, P, H, H), T)), b
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,N,L,B,C,M,H,h,P", [("conv", 4096, 2, 1, 3, 4, 64, 5, 2),
+                                                  ("conv", 2048, 2, 2, 2, 3, 46, 3, 1),
+                                                  ("dx", 1024, 2, 1, 2, 2, 32, 3, 1)])
+def test_windowed_layers_parity_and_decrypt(gpu_lib, kind, N, L, B, C, M, H, h, P):
+    # maps whose single channel does not fit one polynomial are split into
+    # windows (Section 3.3): the plan's windows are the oracle's, every output
+    # ciphertext matches the oracle's ring products over the window term lists,
+    # and the overlap-added decryption is the plaintext layer mod t
+    he = gpu_lib
+    ctx = he.Context(N, L)
+    Ho = H + 2 * P - h + 1
+    if kind == "conv":
+        plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+        x = synth.int8_uniform(synth.rng(85, synth.STREAM_ACT, N), (B, C, H, H))
+        w = synth.int8_uniform(synth.rng(85, synth.STREAM_PT, N), (M, C, h, h))
+        g = packing.WindowGeometry(C, M, H, H, h, P, N)
+        w_eq, M_out = w, M
+    else:
+        plan = he.Plan(ctx, he.HE_KIND_DX, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+        x = synth.int8_uniform(synth.rng(86, synth.STREAM_ACT, N), (B, M, Ho, Ho))        # dY
+        w = synth.int8_uniform(synth.rng(86, synth.STREAM_PT, N), (M, C, h, h))
+        g = packing.WindowGeometry(M, C, Ho, Ho, h, h - 1 - P, N)
+        w_eq, M_out = np.ascontiguousarray(np.transpose(w, (1, 0, 2, 3))[:, :, ::-1, ::-1]), C
+    info = plan.info
+    assert g.tiles > 1
+    for k in ("O", "S", "Cw", "cb", "Hw", "Ww", "tiles"):
+        assert info[k] == getattr(g, k), k
+    polys = np.stack([g.pack_input(x[b]) for b in range(B)])                    # [B, tiles, cb, N]
+    lib_polys = he.he_pack_input(plan.h, x.reshape(-1), polys.size)
+    assert np.array_equal(lib_polys, polys.reshape(-1))
+    ct, s = encrypt_polys(ctx, polys, 85)
+    pt = core.lift(g.pack_weight(w_eq).reshape(-1, N), ctx.q)
+    row, cti, pti = g.terms(B)
+    expect = core.csr_cpmul(ct, pt, row, cti, pti, ctx.q, ctx.psi, method=2)
+    got = run_layer(he, ctx, plan, ct, torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda())
+    assert_equal_u64(got, expect, "%s windows" % kind)
+    dec = np.stack([bfv.decrypt(got[o], s, ctx.q, ctx.psi, T) for o in range(got.shape[0])])
+    Hout = info["Hout"]
+    y = np.remainder(he.he_extract_output(plan.h, dec, B * M_out * Hout * Hout), T).reshape(B, M_out, Hout, Hout)
+    for b in range(B):
+        if kind == "conv":
+            ref = plain.conv2d(x[b], w, P)
+        else:
+            ref = plain.conv2d_input_grad(x[b], w, P, H, H)
+        assert np.array_equal(y[b], plain.mod_t(ref, T)), b
