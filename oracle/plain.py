@@ -8,6 +8,21 @@ mod t into [0, t).
 import numpy as np
 
 
+def conv2d_strided(x, w, P, stride):
+    """y[m, y, z] = sum over c, a, b of xpad[c, y*stride + a, z*stride + b] * w[m, c, a, b]."""
+    C, H, W = x.shape
+    M, _, h, _ = w.shape
+    xp = np.zeros((C, H + 2 * P, W + 2 * P), dtype=np.int64)
+    xp[:, P:P + H, P:P + W] = x
+    Ho, Wo = (H + 2 * P - h) // stride + 1, (W + 2 * P - h) // stride + 1
+    y = np.zeros((M, Ho, Wo), dtype=np.int64)
+    for yy in range(Ho):
+        for zz in range(Wo):
+            patch = xp[:, yy * stride:yy * stride + h, zz * stride:zz * stride + h]
+            y[:, yy, zz] = np.einsum("mcab,cab->m", w.astype(np.int64), patch)
+    return y
+
+
 def conv2d(x, w, P):
     """x[C, H, W], w[M, C, h, h], stride 1, zero padding P -> y[M, Ho, Wo] (int64)."""
     C, H, W = x.shape

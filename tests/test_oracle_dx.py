@@ -45,3 +45,17 @@ def test_packed_input_grad_through_ring_products():
             acc = (acc + core.negacyclic_mul(np.remainder(xin[k], T), np.remainder(pw[c, k], T), T).astype(np.int64)) % T
         got = packing.conv_extract(acc, geo)
         assert np.array_equal(got, plain.mod_t(plain.conv2d_input_grad(dy, w, P, H, H)[c], T)), c
+
+
+@pytest.mark.parametrize("stride,P,H,h", [(2, 1, 9, 3), (3, 0, 11, 3), (2, 2, 8, 5)])
+def test_strided_conv_matches_torch_and_subsamples_the_correlation(stride, P, H, h):
+    # a stride only subsamples the full correlation that the packed product holds
+    g = np.random.Generator(np.random.PCG64(95 + stride + H))
+    x = g.integers(-9, 10, size=(2, H, H))
+    w = g.integers(-9, 10, size=(3, 2, h, h))
+    y = plain.conv2d_strided(x, w, P, stride)
+    ref = torch.nn.functional.conv2d(torch.from_numpy(x[None]).double(), torch.from_numpy(w).double(),
+                                     stride=stride, padding=P)[0]
+    assert np.array_equal(y, ref.round().long().numpy())
+    full = plain.conv2d(x, w, P)
+    assert np.array_equal(y, full[:, ::stride, ::stride])
