@@ -166,8 +166,10 @@ typedef struct {
   uint32_t C, M;         /* input / output channels (CONV, DW; DX: of the forward layer) */
   uint32_t H, W;         /* input map (CONV, DW; DX: of the forward layer) */
   uint32_t h;            /* kernel side (CONV, DW, DX: the forward kernel) */
-  uint32_t P;            /* zero padding, stride 1 */
+  uint32_t P;            /* zero padding */
   uint32_t n_in, n_out;  /* FC sizes */
+  uint32_t stride;       /* CONV: output stride (0 or 1: none); the packed product holds every
+                            position, so a stride only subsamples the extraction; DW, DX: 0 or 1 */
 } he_conv_shape;
 
 typedef struct {
@@ -178,7 +180,7 @@ typedef struct {
   uint32_t S;            /* channel stride span + 1 */
   uint32_t Cw;           /* channels per polynomial, floor(N / S) */
   uint32_t cb;           /* channel blocks, ceil(C / Cw) */
-  uint32_t Hout, Wout;   /* conv output map */
+  uint32_t Hout, Wout;   /* conv output map ((H + 2P - h) / stride + 1) */
   uint32_t n_iw, n_ow;   /* FC: input chunk width, outputs per polynomial */
   uint32_t n_ct_in;      /* ciphertexts read  (CONV: B*cb; DW: B*(cb+M); FC: B*in_ct; DX: B*cb over M) */
   uint32_t n_pt;         /* plaintext polynomials (CONV: M*cb; DW: B*(M+cb); FC: out_ct*in_ct; DX: C*cb) */
@@ -240,7 +242,8 @@ he_status he_expand_c1(he_ctx *ctx, const uint64_t *seed, uint32_t first_ct, uin
 he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys);
 /* Client-side extraction (host): CONV [B][tiles][M][N] -> y [B][M][Hout][Wout]
  * (windowed plans: the tiles' coefficients summed, so values are sums of the
- * given residues -- reduce mod t after extraction);
+ * given residues -- reduce mod t after extraction; with a stride s, output
+ * (y, z) is the correlation coefficient at (y s, z s) of the padded map);
  * FC [B][out_ct][N] -> y [B][n_out]; DW [M][cb][N] -> dW [M][C][Hk][Hk] with
  * Hk = H + 2P - Hout + 1.  Values are taken as given (mod t after decryption). */
 he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *y);

@@ -530,6 +530,7 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
   }
   if (s.kind == HE_KIND_CONV) {
     const uint32_t T = in.tiles ? in.tiles : 1, tw = (s.W + in.Ww - 1) / in.Ww, th = T / tw, h = s.h;
+    const uint32_t sd = s.stride > 1 ? s.stride : 1;   // a stride subsamples the full correlation
     if (T == 1) {
       for (uint32_t b = 0; b < s.B; ++b)
         for (uint32_t m = 0; m < s.M; ++m) {
@@ -537,7 +538,7 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
           for (uint32_t yy = 0; yy < in.Hout; ++yy)
             for (uint32_t zz = 0; zz < in.Wout; ++zz)
               y[(((size_t)b * s.M + m) * in.Hout + yy) * in.Wout + zz] =
-                  poly[(yy + h - 1 - s.P) * in.O + (zz + h - 1 - s.P)];
+                  poly[(yy * sd + h - 1 - s.P) * in.O + (zz * sd + h - 1 - s.P)];
         }
       return HE_OK;
     }
@@ -556,7 +557,7 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
         for (uint32_t yy = 0; yy < in.Hout; ++yy)
           for (uint32_t zz = 0; zz < in.Wout; ++zz)
             y[(((size_t)b * s.M + m) * in.Hout + yy) * in.Wout + zz] =
-                F[(size_t)(yy + h - 1 - s.P) * FW + (zz + h - 1 - s.P)];
+                F[(size_t)(yy * sd + h - 1 - s.P) * FW + (zz * sd + h - 1 - s.P)];
       }
     return HE_OK;
   }

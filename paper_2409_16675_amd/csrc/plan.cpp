@@ -14,6 +14,8 @@ static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p);
 // forward conv of dY [B][M][H_out][W_out] with the kernel transposed in its
 // channels and rotated by 180 degrees, padding h-1-P: its output map is H x W.
 he_status make_plan(const Ctx &c, const he_conv_shape &s, Plan &p) {
+  if (s.stride > 1 && s.kind != HE_KIND_CONV)
+    return fail(HE_EUNSUPPORTED, "a stride applies to forward convolutions only");
   if (s.kind != HE_KIND_DX) {
     p.eq = s;
     return make_plan_geom(c, s, p);
@@ -51,8 +53,9 @@ static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p) {
     if (!s.C || !s.M || !s.H || !s.W || !s.h) return fail(HE_EINVAL, "conv sizes must be positive");
     if (s.H + 2 * s.P < s.h || s.W + 2 * s.P < s.h) return fail(HE_EINVAL, "kernel larger than padded input");
     if (s.P >= s.h) return fail(HE_EINVAL, "padding must be smaller than the kernel");
-    in.Hout = s.H + 2 * s.P - s.h + 1;
-    in.Wout = s.W + 2 * s.P - s.h + 1;
+    const uint32_t stride = s.stride > 1 ? s.stride : 1;
+    in.Hout = (s.H + 2 * s.P - s.h) / stride + 1;
+    in.Wout = (s.W + 2 * s.P - s.h) / stride + 1;
     // the polynomial "kernel" is w (h x h) for CONV and dY (Hout x Hout) for DW
     uint32_t hk = s.h;
     if (s.kind == HE_KIND_DW) {

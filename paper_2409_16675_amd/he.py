@@ -38,7 +38,7 @@ class he_params(ctypes.Structure):
 
 class he_conv_shape(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("B", c_u32), ("C", c_u32), ("M", c_u32), ("H", c_u32), ("W", c_u32), ("h", c_u32),
-                ("P", c_u32), ("n_in", c_u32), ("n_out", c_u32)]
+                ("P", c_u32), ("n_in", c_u32), ("n_out", c_u32), ("stride", c_u32)]
 
 
 class he_plan_info(ctypes.Structure):
@@ -234,8 +234,8 @@ def he_cpmul_acc(ctx, ct, pt, K, acc, flags=0, ws=None, ws_bytes=0, stream=None)
 
 
 # ------------------------------------------------------------------ plans
-def he_plan_create(ctx, kind, B=1, C=0, M=0, H=0, W=0, h=0, P=0, n_in=0, n_out=0):
-    s = he_conv_shape(kind, B, C, M, H, W, h, P, n_in, n_out)
+def he_plan_create(ctx, kind, B=1, C=0, M=0, H=0, W=0, h=0, P=0, n_in=0, n_out=0, stride=0):
+    s = he_conv_shape(kind, B, C, M, H, W, h, P, n_in, n_out, stride)
     h_ = c_void_p()
     _chk(_lib.he_plan_create(ctx, ctypes.byref(s), ctypes.byref(h_)), "he_plan_create")
     return h_

@@ -257,3 +257,35 @@ def test_windowed_layers_parity_and_decrypt(gpu_lib, kind, N, L, B, C, M, H, h, 
         else:
             ref = plain.conv2d_input_grad(x[b], w, P, H, H)
         assert np.array_equal(y[b], plain.mod_t(ref, T)), b
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,L,B,C,M,H,h,P,stride", [(1024, 2, 2, 3, 2, 9, 3, 1, 2), (4096, 2, 1, 3, 2, 64, 5, 2, 2),
+                                                    (2048, 2, 1, 2, 2, 12, 3, 0, 3)])
+def test_strided_conv(gpu_lib, N, L, B, C, M, H, h, P, stride):
+    # a stride subsamples the correlation the ring product holds: the ciphertexts
+    # equal the unstrided layer's, and the strided extraction of their decryption
+    # is the strided plaintext convolution (also with windows: the 64 x 64 case)
+    he = gpu_lib
+    ctx = he.Context(N, L)
+    p1 = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    ps = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=H, h=h, P=P, stride=stride)
+    info = ps.info
+    assert info["Hout"] == (H + 2 * P - h) // stride + 1
+    for k in ("n_ct_in", "n_pt", "n_ct_out", "n_terms", "O", "S", "tiles"):
+        assert info[k] == p1.info[k], k
+    x = synth.int8_uniform(synth.rng(88, synth.STREAM_ACT, N), (B, C, H, H))
+    w = synth.int8_uniform(synth.rng(88, synth.STREAM_PT, N), (M, C, h, h))
+    polys = he.he_pack_input(ps.h, x.reshape(-1), info["n_ct_in"] * N).reshape(-1, N)
+    ct, s = encrypt_polys(ctx, polys, 88)
+    d_w = torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda()
+    got = run_layer(he, ctx, ps, ct, d_w)
+    assert_equal_u64(got, run_layer(he, ctx, p1, ct, d_w), "strided vs unstrided ciphertexts")
+    dec = np.stack([bfv.decrypt(got[o], s, ctx.q, ctx.psi, T) for o in range(got.shape[0])])
+    Ho = info["Hout"]
+    y = np.remainder(he.he_extract_output(ps.h, dec, B * M * Ho * Ho), T).reshape(B, M, Ho, Ho)
+    for b in range(B):
+        assert np.array_equal(y[b], plain.mod_t(plain.conv2d_strided(x[b], w, P, stride), T)), b
+    with pytest.raises(he.HeError) as ei:
+        he.Plan(ctx, he.HE_KIND_DX, B=B, C=C, M=M, H=H, W=H, h=h, P=P, stride=stride)
+    assert ei.value.status == he.HE_EUNSUPPORTED
