@@ -249,8 +249,11 @@ __all__ = [n for n in dir() if not n.startswith("_") and n not in ("math", "np")
 # adds into F at offset (r*H_w, s*W_w) (overlap-add: F is linear in x) and then
 # crops by P.  The window is the one minimising the CPMul count
 # ceil(H/H_w) * ceil(W/W_w) * cb * M subject to span_w + 1 <= N; ties go to fewer
-# input ciphertexts, then larger H_w, then larger W_w.  Without a need to split
-# (the whole map fits) the single-tile geometry is the plain one.
+# input ciphertexts, then larger H_w, then larger W_w.  The whole map is one of
+# the admissible windows (H_w = H, W_w = W: the plain geometry), so a map that
+# fits is still tiled when tiles pack more channels per polynomial and the
+# count drops (64 x 64 maps with 3 channels at N = 8192: two 32 x 64 tiles with
+# all channels in one polynomial, 6 CPMul for 3 outputs, against 9 unsplit).
 
 
 class WindowGeometry:
@@ -260,25 +263,21 @@ class WindowGeometry:
         self.C, self.M, self.H, self.W, self.h, self.P, self.N = C, M, H, W, h, P, N
         self.Hout = H + 2 * P - h + 1
         self.Wout = W + 2 * P - h + 1
-        try:
-            g = ConvGeometry(C, H, W, h, P, N)
-            self.Hw, self.Ww = H, W
-        except ValueError:
-            best = None
-            for hw in range(1, H + 1):
-                for ww in range(1, W + 1):
-                    O = max(ww, hw) + h - 1
-                    S = (hw + h - 2) * O + (ww + h - 2) + 1
-                    if S > N:
-                        continue
-                    cb = -(-C // (N // S))
-                    tiles = -(-H // hw) * -(-W // ww)
-                    key = (tiles * cb * M, tiles * cb, -hw, -ww)
-                    if best is None or key < best[0]:
-                        best = (key, hw, ww)
-            if best is None:
-                raise ValueError("no window fits one polynomial")
-            self.Hw, self.Ww = best[1], best[2]
+        best = None
+        for hw in range(1, H + 1):
+            for ww in range(1, W + 1):
+                O = max(ww, hw) + h - 1
+                S = (hw + h - 2) * O + (ww + h - 2) + 1
+                if S > N:
+                    continue
+                cb = -(-C // (N // S))
+                tiles = -(-H // hw) * -(-W // ww)
+                key = (tiles * cb * M, tiles * cb, -hw, -ww)
+                if best is None or key < best[0]:
+                    best = (key, hw, ww)
+        if best is None:
+            raise ValueError("no window fits one polynomial")
+        self.Hw, self.Ww = best[1], best[2]
         self.O = max(self.Ww, self.Hw) + h - 1
         self.span = (self.Hw + h - 2) * self.O + (self.Ww + h - 2)
         self.S = self.span + 1

@@ -1,8 +1,9 @@
 """Oracle pins for spatial windows (Section 3.3: an input map that does not fit
 one ring element is split into windows): the tiled packing with overlap-add
 reproduces the plaintext convolution exactly through ring products at forced
-small degrees, the chosen window is the cheapest feasible one, and a map that
-fits needs no split."""
+small degrees, the chosen window is the cheapest feasible one (the whole map
+being one of the candidates), a map that fits stays whole unless tiles lower
+the count, and then the tiled layer still reproduces the convolution."""
 import numpy as np
 import pytest
 
@@ -56,7 +57,27 @@ def test_window_choice_is_the_cheapest_feasible():
     assert g.span + 1 <= N and (g.tiles, g.cb) == (4, 1)
 
 
-def test_no_split_when_the_map_fits():
-    g = packing.WindowGeometry(3, 16, 32, 32, 3, 1, 8192)
-    ref = packing.ConvGeometry(3, 32, 32, 3, 1, 8192)
-    assert g.tiles == 1 and (g.O, g.S, g.Cw, g.cb) == (ref.O, ref.S, ref.Cw, ref.cb)
+def test_no_split_when_the_whole_map_is_cheapest():
+    for args in [(3, 16, 32, 32, 3, 1, 8192), (16, 32, 16, 16, 3, 1, 4096), (10, 3, 6, 6, 3, 2, 1024)]:
+        C, M, H, W, h, P, N = args
+        g = packing.WindowGeometry(*args)
+        ref = packing.ConvGeometry(C, H, W, h, P, N)
+        assert g.tiles == 1 and (g.O, g.S, g.Cw, g.cb) == (ref.O, ref.S, ref.Cw, ref.cb), args
+
+
+def test_a_fitting_map_is_tiled_when_that_lowers_the_count():
+    # 3 channels of 64 x 64 at N = 8192: one channel per polynomial unsplit
+    # (9 CPMul), all three in each of two 32 x 64 tiles (6 CPMul)
+    unsplit = packing.ConvGeometry(3, 64, 64, 5, 2, 8192)
+    g = packing.WindowGeometry(3, 3, 64, 64, 5, 2, 8192)
+    assert unsplit.cb * 3 == 9
+    assert (g.tiles, g.cb, g.tiles * g.cb * 3) == (2, 1, 6)
+    # the same at a small degree, through ring products
+    C, M, H, W, h, P, N = 3, 2, 10, 10, 3, 1, 256
+    assert packing.ConvGeometry(C, H, W, h, P, N).cb == 3
+    g0 = np.random.Generator(np.random.PCG64(97))
+    x = g0.integers(-4, 5, size=(C, H, W))
+    w = g0.integers(-4, 5, size=(M, C, h, h))
+    g, got = _conv_through_windows(x, w, P, N)
+    assert (g.tiles, g.cb) == (2, 1)
+    assert np.array_equal(got, plain.conv2d(x, w, P))
