@@ -186,21 +186,27 @@ typedef struct {
   uint32_t n_pt;         /* plaintext polynomials (CONV: M*cb; DW: B*(M+cb); FC: out_ct*in_ct; DX: C*cb) */
   uint32_t n_ct_out;     /* ciphertexts written (CONV: B*M; DW: M*cb; FC: B*out_ct; DX: B*C) */
   uint32_t n_terms;      /* CPMul count */
-  uint32_t Hw, Ww;       /* CONV, DX: input window (the whole map unless it does not fit one polynomial) */
+  uint32_t Hw, Ww;       /* CONV, DX: input window (the whole map unless tiles are cheaper or it does not fit) */
   uint32_t tiles;        /* CONV, DX: windows per input map; inputs and outputs are per (b, tile): the
                             counts above are then B*tiles*cb and B*tiles*M (DX: B*tiles*C) */
 } he_plan_info;
 
 /* Plan a layer on a context.  Allocates host memory and a small device copy of
- * the term lists on the context's device.  A CONV or DX map whose single
- * channel does not fit one polynomial is split into windows (Section 3.3):
- * disjoint H_w x W_w tiles of the unpadded input with pitch
- * O = max(W_w, H_w) + h - 1, chosen to minimise the CPMul count (ties: fewer
- * input ciphertexts, then larger H_w, then larger W_w); he_extract_output
- * overlap-adds the tiles' products.  HE_EUNSUPPORTED when no window fits, or
- * when a weight-gradient (DW) channel does not fit. */
+ * the term lists on the context's device.  A CONV or DX map is packed in
+ * windows (Section 3.3): disjoint H_w x W_w tiles of the unpadded input with
+ * pitch O = max(W_w, H_w) + h - 1, chosen among all windows that fit one
+ * polynomial (the whole map is one) to minimise the CPMul count (ties: fewer
+ * input ciphertexts, then larger H_w, then larger W_w); a map whose channel
+ * does not fit is always split, one that fits only when tiles lower the count.
+ * he_extract_output overlap-adds the tiles' products.  HE_EUNSUPPORTED when no
+ * window fits, or when a weight-gradient (DW) channel does not fit. */
 he_status he_plan_create(const he_ctx *ctx, const he_conv_shape *shape, he_plan **out);
 he_status he_plan_destroy(he_plan *plan);
+/* Host-only planning (Section 3.3): the geometry and counts he_plan_create would
+ * give on a context of ring degree N, without a context, device or allocation.
+ * N a power of two in [16, 2^15], else HE_EINVAL; shape errors as he_plan_create.
+ * For sizing and for multiplication-count studies (n_terms is the CPMul count). */
+he_status he_plan_query(uint32_t N, const he_conv_shape *shape, he_plan_info *info);
 he_status he_plan_get_info(const he_plan *plan, he_plan_info *info);
 /* Host copies of the term lists: output o sums terms [row[o], row[o+1]) of
  * ct_in[ct_idx[t]] (x) pt[pt_idx[t]].  row [n_ct_out+1], ct_idx/pt_idx [n_terms]. */

@@ -322,6 +322,17 @@ he_status he_plan_create(const he_ctx *ctx, const he_conv_shape *shape, he_plan 
   return HE_OK;
 }
 
+he_status he_plan_query(uint32_t N, const he_conv_shape *shape, he_plan_info *info) {
+  if (!shape || !info) return fail(HE_EINVAL, "null argument");
+  if (N < 16 || N > 32768 || (N & (N - 1))) return fail(HE_EINVAL, "N must be a power of two in [16, 2^15]");
+  Ctx c;
+  c.N = N;
+  Plan p;
+  he_status s = make_plan(c, *shape, p);
+  if (s == HE_OK) *info = p.info;
+  return s;
+}
+
 he_status he_plan_destroy(he_plan *plan) {
   if (!plan) return HE_OK;
   if (plan->p.d_terms) (void)hipFree(plan->p.d_terms);

@@ -67,11 +67,14 @@ static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p) {
     in.Ww = s.W;
     in.O = std::max(s.W, s.H) + hk - 1;
     in.span = (s.H + hk - 2) * in.O + (s.W + hk - 2);
-    if (in.span + 1 > N) {
+    if (s.kind == HE_KIND_DW && in.span + 1 > N)
+      return fail(HE_EUNSUPPORTED, "weight-gradient channel does not fit one polynomial");
+    if (s.kind == HE_KIND_CONV) {
       // spatial windows (Section 3.3, garbled objective; reading): disjoint
       // tiles, the cheapest in CPMul count that fit, ties to fewer input
-      // ciphertexts, then larger H_w, then larger W_w
-      if (s.kind != HE_KIND_CONV) return fail(HE_EUNSUPPORTED, "weight-gradient channel does not fit one polynomial");
+      // ciphertexts, then larger H_w, then larger W_w.  The whole map is one
+      // candidate, so a map that fits is tiled only when tiles pack more
+      // channels per polynomial and lower the count.
       uint64_t best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
       for (uint32_t hw = 1; hw <= s.H; ++hw)
         for (uint32_t ww = 1; ww <= s.W; ++ww) {

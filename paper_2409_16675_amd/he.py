@@ -64,6 +64,7 @@ _SIGS = {
     "he_plan_create": [c_void_p, ctypes.POINTER(he_conv_shape), ctypes.POINTER(c_void_p)],
     "he_plan_destroy": [c_void_p],
     "he_plan_get_info": [c_void_p, ctypes.POINTER(he_plan_info)],
+    "he_plan_query": [c_u32, ctypes.POINTER(he_conv_shape), ctypes.POINTER(he_plan_info)],
     "he_plan_terms": [c_void_p, i32p, i32p, i32p],
     "he_workspace_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
     "he_corr_conv2d": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
@@ -248,6 +249,14 @@ def he_plan_destroy(plan):
 def he_plan_get_info(plan):
     i = he_plan_info()
     _chk(_lib.he_plan_get_info(plan, ctypes.byref(i)), "he_plan_get_info")
+    return {n: getattr(i, n) for n, _ in he_plan_info._fields_}
+
+
+def he_plan_query(N, kind, B=1, C=0, M=0, H=0, W=0, h=0, P=0, n_in=0, n_out=0, stride=0):
+    """Plan info for ring degree N without a context or device (host only)."""
+    s = he_conv_shape(kind, B, C, M, H, W, h, P, n_in, n_out, stride)
+    i = he_plan_info()
+    _chk(_lib.he_plan_query(N, ctypes.byref(s), ctypes.byref(i)), "he_plan_query")
     return {n: getattr(i, n) for n, _ in he_plan_info._fields_}
 
 

@@ -214,10 +214,12 @@ def test_input_gradient_parity_and_decrypt(gpu_lib, N, L, B, C, M, H, h, P):
 @pytest.mark.gpu
 @pytest.mark.parametrize("kind,N,L,B,C,M,H,h,P", [("conv", 4096, 2, 1, 3, 4, 64, 5, 2),
                                                   ("conv", 2048, 2, 2, 2, 3, 46, 3, 1),
-                                                  ("dx", 1024, 2, 1, 2, 2, 32, 3, 1)])
+                                                  ("dx", 1024, 2, 1, 2, 2, 32, 3, 1),
+                                                  ("conv", 8192, 3, 2, 3, 3, 64, 5, 2)])
 def test_windowed_layers_parity_and_decrypt(gpu_lib, kind, N, L, B, C, M, H, h, P):
-    # maps whose single channel does not fit one polynomial are split into
-    # windows (Section 3.3): the plan's windows are the oracle's, every output
+    # maps split into windows (Section 3.3), because one channel does not fit
+    # one polynomial or (the last case) because two 32 x 64 tiles holding all
+    # three channels take fewer products: the plan's windows are the oracle's, every output
     # ciphertext matches the oracle's ring products over the window term lists,
     # and the overlap-added decryption is the plaintext layer mod t
     he = gpu_lib
