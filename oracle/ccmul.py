@@ -64,12 +64,15 @@ def _product_primes(N, bound):
         n += 1
 
 
-def tensor(pairs, q):
+def tensor(pairs, q, N_empty=0):
     """Exact x0, x1, x2 (lists of N integers) of the sum over (a, b) in pairs of a (x) b.
 
     pairs: list of (a [2, L, N], b [2, L, N]) residue arrays.  Modulo each
     product prime the sums are term-list products of the oracle's C path:
-    output 0 = sum a (x) b0 = (sum a0 b0, sum a1 b0), output 1 = sum a (x) b1."""
+    output 0 = sum a (x) b0 = (sum a0 b0, sum a1 b0), output 1 = sum a (x) b1.
+    An empty list is the empty sum, zero (N must then be given)."""
+    if not pairs:
+        return [[0] * N_empty for _ in range(3)]
     L, N = pairs[0][0].shape[1:]
     Q = bfv.modulus(q)
     n = len(pairs)
@@ -153,7 +156,7 @@ def ccmul_acc(a_cts, b_cts, row, a_idx, b_idx, rlk, q, psi, t):
     outs = []
     for o in range(len(row) - 1):
         pairs = [(a_cts[a_idx[k]], b_cts[b_idx[k]]) for k in range(row[o], row[o + 1])]
-        x = tensor(pairs, q)
+        x = tensor(pairs, q, a_cts.shape[-1])
         d = [residues(scale_round(xc, Q, t), q) for xc in x]
         outs.append(relinearize(d[0], d[1], d[2], rlk, q, psi))
     return np.stack(outs)

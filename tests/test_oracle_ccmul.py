@@ -180,3 +180,14 @@ def test_noise_at_the_benchmark_ring():
     assert np.array_equal(bfv.decrypt(out, s, q, psi, T), want)
     Q = bfv.modulus(q)
     assert bfv.noise_bits(out, s, want, q, psi, T) < (Q // (2 * T)).bit_length() - 40
+
+
+def test_an_output_without_terms_is_the_zero_ciphertext():
+    # the empty sum: no tensor, d = 0, and relinearizing zero digits adds nothing
+    N, L = 256, 2
+    q, psi, g, s = _keys(N, L, 50, 76)
+    rlk, _, _ = _rlk(s, q, psi, g)
+    cts = np.stack([_enc(g.integers(0, T, size=N), s, q, psi, g, N) for _ in range(2)])
+    out = ccmul.ccmul_acc(cts, cts, [0, 1, 1], [0], [1], rlk, q, psi, T)
+    assert not out[1].any()
+    assert not bfv.decrypt(out[1], s, q, psi, T).any()
