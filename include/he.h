@@ -254,6 +254,41 @@ he_status he_pack_input(const he_plan *plan, const int32_t *x, int64_t *polys);
  * Hk = H + 2P - Hout + 1.  Values are taken as given (mod t after decryption). */
 he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *y);
 
+/* ------------------------------- ciphertext-ciphertext product (CCMul) */
+/* The server's preprocessing step of Section 3.2 (CryptoTrain-P): products of
+ * ciphertexts, [r_x][r_w] -> [r_x r_w], in the BFV scheme of the layer
+ * ciphertexts, relinearized back to two components:
+ *   out[o] = Relin( round(t/Q * sum over terms k of o of a[a_idx[k]] (x) b[b_idx[k]]) )  mod Q
+ * where (x) is the tensor product (c0 d0, c0 d1 + c1 d0, c1 d1) of the
+ * ciphertexts' coefficients read as centred integers in (-Q/2, Q/2], exact
+ * over the integers, and round is to the nearest integer; one rounding and one
+ * relinearization per output.  Relinearization is RNS-digit key switching:
+ *   Relin(d0, d1, d2) = (d0, d1) + sum_j [d2]_{q_j} rlk_j,
+ *   rlk_j = ([-(a_j s + e_j) + g_j s^2]_Q, a_j),  g_j = (Q/q_j) [(Q/q_j)^-1]_{q_j}
+ * with [d2]_{q_j} the residue of d2 mod q_j taken as an integer in [0, q_j).
+ * a      device [n_a][2][L][N] and b device [n_b][2][L][N], canonical residues;
+ * row    host int32 [n_out + 1], a_idx and b_idx host int32 [row[n_out]]: output
+ *        o sums terms row[o] .. row[o+1]-1 (at most 65536; HE_EUNSUPPORTED
+ *        beyond); row NULL: pairwise products out[k] = a[k] (x) b[k] with
+ *        n_out = n_a = n_b (HE_EINVAL otherwise); indexes out of range: HE_EINVAL;
+ * rlk_hat device [L][2][L][N]: the key in the transformed domain (he_ntt_fwd
+ *        of its L*2*L planes), read only;
+ * out    device [n_out][2][L][N], written (must not alias the inputs).
+ * flags: HE_VALIDATE (HE_ERANGE if a, b or rlk_hat is not canonical).
+ * ws: device, he_ccmul_ws_size() bytes for the same sizes and flags.
+ * The exact rounding runs on an extended base Q u P of auxiliary primes with
+ * log2 P >= log2 t + log2 N + log2 Q + 18, built with its conversion constants
+ * on first use (device memory owned by the context); HE_EUNSUPPORTED if that
+ * base would need more than 16 primes in all or more than 8 auxiliary ones.
+ * The term lists are copied to the workspace and the call waits for that
+ * copy; the rest is asynchronous on stream. */
+he_status he_ccmul_ws_size(he_ctx *ctx, uint32_t n_a, uint32_t n_b, uint32_t n_out, uint32_t n_terms,
+                           uint32_t flags, size_t *bytes);
+he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t *b, uint32_t n_b,
+                   const int32_t *row, const int32_t *a_idx, const int32_t *b_idx, uint32_t n_out,
+                   const uint64_t *rlk_hat, uint64_t *out, uint32_t flags, void *ws, size_t ws_bytes,
+                   void *stream);
+
 /* -------------------------------------------- plaintext product (PPMul) */
 /* The server's plaintext product of the online linear-layer protocol (Section
  * 3.2): with the client's masked operands (x - r_x) and (w - r_w) it returns

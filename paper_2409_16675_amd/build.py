@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhe.so")
 
-SOURCES = ["kernels.hip", "persistent.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "persistent.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp", "ccmul.hip", "ccmul.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-ffp-contract=off",

@@ -5,8 +5,6 @@
 #include "plan.hpp"
 
 namespace he {
-he_status build_context(const he_params *p, Ctx **out);
-void free_context(Ctx *c);
 he_status client_decrypt_crt(const Ctx &c, const uint64_t *x, uint32_t n_ct, int64_t *m);
 
 static thread_local std::string g_err;
@@ -181,7 +179,10 @@ he_status he_cpmul_acc_ws(const he_ctx *ctx, uint32_t K, uint32_t flags, size_t 
   return HE_OK;
 }
 
-static he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes, void *flag_mem, hipStream_t st) {
+}  // extern "C"
+
+namespace he {
+he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes, void *flag_mem, hipStream_t st) {
   uint32_t *bad = (uint32_t *)flag_mem;
   HIPCHK(hipMemsetAsync(bad, 0, 4, st), "validate memset");
   HIPCHK(launch_check_canonical(c, planes, n_planes, bad, st), "validate launch");
@@ -191,6 +192,9 @@ static he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes,
   if (h) return fail(HE_ERANGE, std::to_string(h) + " coefficients outside [0, q_i)");
   return HE_OK;
 }
+}  // namespace he
+
+extern "C" {
 
 // ---------------------------------------------------------------- plaintext product
 // The ring of the plaintext modulus: one prime q = t (an NTT-friendly t such

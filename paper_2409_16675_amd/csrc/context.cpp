@@ -1,6 +1,7 @@
 // Context set-up: RNS primes, roots, twiddle tables and per-prime constants.
 #include <cstring>
 #include <mutex>
+#include <string>
 
 #include "he_internal.hpp"
 
@@ -64,11 +65,15 @@ uint64_t least_root(uint64_t q, uint32_t N) {
 }
 }  // namespace
 
-he_status build_context(const he_params *p, Ctx **out) {
+bool is_prime64(uint64_t n) { return prime64(n); }
+
+// max_L: 8 for contexts of the API; internal rings (the extended base of the
+// ciphertext-ciphertext product) allow up to 16 primes
+he_status build_context(const he_params *p, Ctx **out, uint32_t max_L) {
   if (!p || !out) return fail(HE_EINVAL, "null argument");
   const uint32_t N = p->N, L = p->L;
   if (N < 1024 || N > 16384 || (N & (N - 1))) return fail(HE_EINVAL, "N must be a power of two in [1024, 16384]");
-  if (L < 1 || L > 8) return fail(HE_EINVAL, "L must be in [1, 8]");
+  if (L < 1 || L > max_L) return fail(HE_EINVAL, "L must be in [1, " + std::to_string(max_L) + "]");
   if (p->t < 2 || p->t >= (1ull << 32)) return fail(HE_EINVAL, "t must be in [2, 2^32)");
   Ctx *c = new Ctx();
   c->N = N;
@@ -201,6 +206,11 @@ he_status build_context(const he_params *p, Ctx **out) {
 void free_context(Ctx *c) {
   if (!c) return;
   if (c->tctx) free_context(c->tctx);
+  if (c->ectx) free_context(c->ectx);
+  if (c->d_conv) {
+    (void)hipSetDevice(c->device);
+    (void)hipFree(c->d_conv);
+  }
   (void)hipSetDevice(c->device);
   for (void *p : {(void *)c->d_primes, c->d_tw_f64_fwd, c->d_tw_f64_inv, c->d_tw_u64_fwd, c->d_tw_u64_inv})
     if (p) (void)hipFree(p);

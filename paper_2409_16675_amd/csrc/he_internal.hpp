@@ -46,7 +46,19 @@ struct Ctx {
   // the plaintext product; owned by this context
   Ctx *tctx = nullptr;
   std::mutex tctx_mu;
+  // extended base Q u P of the ciphertext-ciphertext product (primes of this
+  // context first) and its exact conversion constants (device RnsConv),
+  // built on first use; owned by this context
+  Ctx *ectx = nullptr;
+  void *d_conv = nullptr;
+  std::mutex ectx_mu;
 };
+
+he_status build_context(const he_params *p, Ctx **out, uint32_t max_L = 8);
+void free_context(Ctx *c);
+bool is_prime64(uint64_t n);
+// HE_ERANGE unless every coefficient of the [n][L][N] planes is below its prime
+he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes, void *flag_mem, hipStream_t st);
 
 enum KernelKind { KK_FWD = 0, KK_FWD_LIFT = 1, KK_INV = 2, KK_MAC_INV = 3, KK_MAC = 4, KK_PACK = 5, KK_PERSIST = 6 };
 

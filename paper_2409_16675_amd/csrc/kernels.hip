@@ -403,14 +403,10 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
       const uint32_t chunk = (la.grid + 7) / 8;
       const unsigned grid = chunk * 8;
       if (la.ncomp == 1) {
-        // single-component products (plaintext polynomials): fp64 arithmetic only
-        if constexpr (std::is_same_v<A, ArF64>) {
-          if ((e = prep(k_mac_inv<A, LOGN, LOGT, false, 1>, lds)) != hipSuccess) return e;
-          hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false, 1>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in,
-                             la.pt, la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
-        } else {
-          return hipErrorInvalidValue;
-        }
+        // single-component products (plaintext polynomials, tensor slots)
+        if ((e = prep(k_mac_inv<A, LOGN, LOGT, false, 1>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false, 1>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in,
+                           la.pt, la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
       } else if (la.accumulate) {
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, true>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, true>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,

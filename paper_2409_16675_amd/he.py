@@ -65,6 +65,9 @@ _SIGS = {
     "he_plan_destroy": [c_void_p],
     "he_plan_get_info": [c_void_p, ctypes.POINTER(he_plan_info)],
     "he_plan_query": [c_u32, ctypes.POINTER(he_conv_shape), ctypes.POINTER(he_plan_info)],
+    "he_ccmul_ws_size": [c_void_p, c_u32, c_u32, c_u32, c_u32, c_u32, ctypes.POINTER(c_size)],
+    "he_ccmul": [c_void_p, c_void_p, c_u32, c_void_p, c_u32, i32p, i32p, i32p, c_u32, c_void_p, c_void_p, c_u32,
+                 c_void_p, c_size, c_void_p],
     "he_plan_terms": [c_void_p, i32p, i32p, i32p],
     "he_workspace_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
     "he_corr_conv2d": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
@@ -308,6 +311,26 @@ def he_ppmul(ctx, plan, a, b, out, flags=0, ws=None, ws_bytes=0, stream=None):
     """out[o] = sum over the plan's terms of a[cti] * b[pti] in Z_t[X]/(X^N+1) (device buffers)."""
     _chk(_lib.he_ppmul(ctx, plan, _ptr(a), _ptr(b), _ptr(out), flags, _ptr(ws), ws_bytes, _stream(stream)),
          "he_ppmul")
+
+
+def he_ccmul_ws_size(ctx, n_a, n_b, n_out, n_terms, flags=0):
+    b = c_size()
+    _chk(_lib.he_ccmul_ws_size(ctx, n_a, n_b, n_out, n_terms, flags, ctypes.byref(b)), "he_ccmul_ws_size")
+    return b.value
+
+
+def he_ccmul(ctx, a, n_a, b, n_b, row, a_idx, b_idx, n_out, rlk_hat, out, flags=0, ws=None, ws_bytes=0, stream=None):
+    """out[o] = Relin(round(t/Q * sum over terms of a[a_idx] (x) b[b_idx])) (device ciphertexts; host
+    int32 term lists, row None for pairwise products)."""
+    if row is None:
+        rp = ap = bp = None
+    else:
+        row = np.ascontiguousarray(row, dtype=np.int32)
+        a_idx = np.ascontiguousarray(a_idx, dtype=np.int32)
+        b_idx = np.ascontiguousarray(b_idx, dtype=np.int32)
+        rp, ap, bp = (v.ctypes.data_as(i32p) for v in (row, a_idx, b_idx))
+    _chk(_lib.he_ccmul(ctx, _ptr(a), n_a, _ptr(b), n_b, rp, ap, bp, n_out, _ptr(rlk_hat), _ptr(out), flags, _ptr(ws),
+                       ws_bytes, _stream(stream)), "he_ccmul")
 
 
 def he_pack_input(plan, x, n_out_words):
