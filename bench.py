@@ -245,6 +245,46 @@ def time_ppmul(he, torch, wl, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def time_ccmul(he, torch, wl, steps, warmup):
+    """The preprocessing product of CryptoTrain-P (Section 3.2) for the same layer:
+    [r_x r_w] for its 256 outputs, each the relinearized product of one of the 16
+    input-side by one of the 16 weight-side mask ciphertexts (the plan's term
+    lists).  Ciphertexts and key are uniform residues of the right shapes (the
+    work does not depend on their values; the tests check the arithmetic).
+    Returns seconds per layer and the per-kernel-kind profile of one call."""
+    import numpy as np
+    from paper_2409_16675_amd import synth
+    ctx, plan, info, N, L = wl["ctx"], wl["plan"], wl["info"], wl["N"], wl["L"]
+    row, cti, pti = he.he_plan_terms(plan.h)
+    g = synth.rng(2, synth.STREAM_MASK, 1)
+    a = he.to_device_u64(synth.uniform_residues(g, (info["n_ct_in"], 2), ctx.q, N))
+    b = he.to_device_u64(synth.uniform_residues(g, (info["n_pt"], 2), ctx.q, N))
+    rlk = he.to_device_u64(synth.uniform_residues(g, (L, 2), ctx.q, N))
+    n_out = info["n_ct_out"]
+    out = he.empty_u64((n_out, 2, L, N))
+    ws = he.workspace(he.he_ccmul_ws_size(ctx.h, info["n_ct_in"], info["n_pt"], n_out, len(cti), 0))
+    stream = torch.cuda.current_stream()
+
+    def call():
+        he.he_ccmul(ctx.h, a, info["n_ct_in"], b, info["n_pt"], row, cti, pti, n_out, rlk, out, 0, ws, ws.numel(),
+                    stream)
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    he.he_ctx_profile(ctx.h, True)
+    call()
+    torch.cuda.synchronize()
+    he.he_ctx_profile(ctx.h, False)
+    prof = he.he_ctx_profile_read(ctx.h)
+    return dt, n_out, {k: dict(launches=v["launches"], total_us=round(v["total_ms"] * 1e3, 1)) for k, v in prof.items()}
+
+
 def ntt_rate(he, torch, wl, iters=20):
     ctx = wl["ctx"]
     n_polys = 512
@@ -422,6 +462,7 @@ def main():
         torch.cuda.synchronize()
         same = same and bool(torch.equal(outs[j].view(torch.int64), ref.view(torch.int64)))
     seeded_dt, seeded_same = time_seeded(he, torch, wl, max(5, args.steps // 2), args.warmup)
+    cc_dt, cc_n, cc_prof = time_ccmul(he, torch, wl, max(5, args.steps // 5), min(args.warmup, 3))
     res = {
         "metric": METRIC, "value": round(n_cpmul / dt, 1), "unit": "CPMul-acc/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
@@ -437,6 +478,11 @@ def main():
         "seeded_c1": {"fused_ms_per_step": round(seeded_dt * 1e3, 4), "equals_full_ciphertext_layer": seeded_same,
                       "input_bytes_per_step": wl["info"]["n_ct_in"] * wl["L"] * wl["N"] * 8,
                       "input_bytes_per_step_unseeded": wl["info"]["n_ct_in"] * 2 * wl["L"] * wl["N"] * 8},
+        "ccmul": {"what": "relinearized ciphertext products [r_x r_w] of the layer's 256 outputs (preprocessing)",
+                  "ms_per_layer": round(cc_dt * 1e3, 4), "us_per_product": round(cc_dt * 1e6 / cc_n, 3),
+                  "cpmul_us_fused": round(fused_dt * 1e6 / n_cpmul, 3), "cpmul_us_batched": round(dt * 1e6 / n_cpmul, 3),
+                  "ratio_to_cpmul_fused": round(cc_dt / fused_dt, 2), "ratio_to_cpmul_batched": round(cc_dt / dt, 2),
+                  "kernels_one_call": cc_prof},
         "kernels_fused_path": {k: dict(v, avg_us=round(v["total_ms"] * 1e3 / v["launches"], 2))
                                for k, v in stats.items()},
         "schedules": {k: {"arith": "f64" if v[0] == 1 else "u64", "coeffs_per_thread": 1 << v[1]}

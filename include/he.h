@@ -446,7 +446,8 @@ he_status he_server_destroy(he_server *s);
  * kernel kind (at most cap entries).  Kinds: 0 forward transform, 1 forward
  * transform of packed plaintexts, 2 inverse transform, 3 fused multiply-
  * accumulate + inverse transform, 4 multiply-accumulate in the transformed
- * domain, 5 packing, 6 persistent batch kernel. */
+ * domain, 5 packing, 6 persistent batch kernel, 7 exact RNS base conversion
+ * (the lift and the scale-and-round of the ciphertext product). */
 typedef struct {
   uint32_t kind;
   uint32_t launches;

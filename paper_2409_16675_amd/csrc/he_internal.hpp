@@ -60,7 +60,7 @@ bool is_prime64(uint64_t n);
 // HE_ERANGE unless every coefficient of the [n][L][N] planes is below its prime
 he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes, void *flag_mem, hipStream_t st);
 
-enum KernelKind { KK_FWD = 0, KK_FWD_LIFT = 1, KK_INV = 2, KK_MAC_INV = 3, KK_MAC = 4, KK_PACK = 5, KK_PERSIST = 6 };
+enum KernelKind { KK_FWD = 0, KK_FWD_LIFT = 1, KK_INV = 2, KK_MAC_INV = 3, KK_MAC = 4, KK_PACK = 5, KK_PERSIST = 6, KK_RNS = 7 };
 
 // Bracket one launch with events when profiling is on: returns the launch's error.
 template <class F>

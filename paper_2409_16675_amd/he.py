@@ -203,7 +203,7 @@ class he_kernel_stat(ctypes.Structure):
     _fields_ = [("kind", c_u32), ("launches", c_u32), ("total_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
-KERNEL_KINDS = {0: "ntt_fwd", 1: "ntt_fwd_lift", 2: "ntt_inv", 3: "mac_inv", 4: "mac", 5: "pack", 6: "persistent"}
+KERNEL_KINDS = {0: "ntt_fwd", 1: "ntt_fwd_lift", 2: "ntt_inv", 3: "mac_inv", 4: "mac", 5: "pack", 6: "persistent", 7: "rns_convert"}
 
 
 def he_ctx_profile(ctx, enable):
