@@ -24,10 +24,10 @@
 #include "rns.hpp"
 
 namespace he {
-hipError_t launch_rns_extend(const RnsConv *d_conv, uint64_t *out, const uint64_t *in, uint32_t n_polys, uint32_t N,
-                             hipStream_t st);
-hipError_t launch_rns_scale_round(const RnsConv *d_conv, uint64_t *out, uint64_t *dig, const uint64_t *X,
-                                  uint32_t n_out, uint32_t N, hipStream_t st);
+hipError_t launch_rns_extend(const RnsConv *d_conv, int L, int K, uint64_t *out, const uint64_t *in,
+                             uint32_t n_polys, uint32_t N, hipStream_t st);
+hipError_t launch_rns_scale_round(const RnsConv *d_conv, int L, int K, uint64_t *out, uint64_t *dig,
+                                  const uint64_t *X, uint32_t n_out, uint32_t N, hipStream_t st);
 
 namespace {
 typedef unsigned __int128 u128;
@@ -320,9 +320,9 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
   uint64_t *X = (uint64_t *)(w + l.x), *dig = (uint64_t *)(w + l.dig);
   const Sched sf{ec->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64, c.s_fwd.loge};
   const Sched sm{ec->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64, c.s_mac.loge};
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, stage, a, n_a * 2, N, st); }), "ccmul extend a");
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), stage, a, n_a * 2, N, st); }), "ccmul extend a");
   HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*ec, sf, a_hat, stage, n_a * 2 * E, st); }), "ccmul fwd a");
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, stage, b, n_b * 2, N, st); }), "ccmul extend b");
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), stage, b, n_b * 2, N, st); }), "ccmul extend b");
   HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*ec, sf, b_hat, stage, n_b * 2 * E, st); }), "ccmul fwd b");
   Terms tt;
   tt.row = d_tl + t_row;
@@ -331,7 +331,7 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
   tt.n_out = n_out * 3;
   HIPCHK(timed(c, st, KK_MAC_INV, [&] { return launch_mac(*ec, sm, X, a_hat, b_hat, tt, false, false, st, 1); }),
          "ccmul tensor");
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_scale_round(cv, out, dig, X, n_out, N, st); }),
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_scale_round(cv, (int)L, (int)(E - L), out, dig, X, n_out, N, st); }),
          "ccmul scale and round");
   HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, X, dig, n_out * L * L, st); }),
          "ccmul fwd digits");
