@@ -55,7 +55,8 @@ def _run(he, ctx, a, b, row, ai, bi, n_out, rlk_hat, flags=0):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(1024, 2, 50), (1024, 3, 50), (2048, 2, 60), (4096, 4, 50)])
+@pytest.mark.parametrize("N,L,bits", [(1024, 2, 50), (1024, 3, 50), (2048, 2, 60), (4096, 4, 50), (1024, 7, 50),
+                                      (1024, 1, 62)])
 def test_pairwise_products_match_oracle(gpu_lib, N, L, bits):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)
@@ -139,6 +140,11 @@ def test_ccmul_errors(gpu_lib):
     big = np.zeros(65537, np.int32)
     with pytest.raises(he.HeError) as ei:                  # too many products for one output
         _run(he, ctx, a, a, [0, 65537], big, big, 1, rlk_hat)
+    assert ei.value.status == he.HE_EUNSUPPORTED
+    # eight 50-bit primes would need nine auxiliary ones: refused
+    ctx8 = he.Context(1024, 8)
+    with pytest.raises(he.HeError) as ei:
+        he.he_ccmul_ws_size(ctx8.h, 1, 1, 1, 1)
     assert ei.value.status == he.HE_EUNSUPPORTED
     bad = a.copy()
     bad[1, 0, 0, 3] = ctx.q[0]                             # not canonical

@@ -100,7 +100,7 @@ def test_cpmul_validate_rejects_out_of_range(gpu_lib):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(2048, 2, 50), (8192, 3, 50), (4096, 3, 60)])
+@pytest.mark.parametrize("N,L,bits", [(2048, 2, 50), (8192, 3, 50), (4096, 3, 60), (1024, 8, 50), (1024, 2, 62)])
 def test_encrypt_decrypt_match_oracle(gpu_lib, N, L, bits):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)

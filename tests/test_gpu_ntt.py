@@ -12,7 +12,8 @@ from oracle import core
 from paper_2409_16675_amd import synth
 from tests.helpers import assert_equal_u64
 
-RINGS = [(1024, 2, 50), (2048, 2, 50), (2048, 2, 54), (4096, 2, 50), (8192, 3, 50), (8192, 3, 60), (16384, 4, 50)]
+RINGS = [(1024, 2, 50), (2048, 2, 50), (2048, 2, 54), (4096, 2, 50), (8192, 3, 50), (8192, 3, 60), (16384, 4, 50),
+         (1024, 8, 50), (2048, 2, 62)]          # the most primes, the widest primes
 
 
 @pytest.mark.gpu
@@ -48,7 +49,7 @@ def test_ntt_every_schedule_matches_oracle(gpu_lib, N, L, bits):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(8192, 3, 50), (4096, 2, 60), (16384, 4, 50)])
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 50), (4096, 2, 60), (16384, 4, 50), (1024, 8, 50), (2048, 2, 62)])
 def test_ntt_edge_values(gpu_lib, N, L, bits):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)
