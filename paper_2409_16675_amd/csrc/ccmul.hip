@@ -3,7 +3,8 @@
 // lift of ciphertexts from base Q to Q u P, and the exact scale-and-round
 // round(t x / Q) from Q u P back to Q with the relinearization digits.
 //
-// Both are one thread per coefficient with a few 64-bit modular products per
+// Both are one thread per coefficient (256-thread blocks, rows of N
+// coefficients along the grid's x dimension) with a few 64-bit modular products per
 // prime, compiled for each pair of base sizes (L, K) so that every loop has
 // its exact trip count.  The conversion constants sit in device memory and
 // are read uniformly by all lanes.
@@ -67,11 +68,10 @@ __device__ __forceinline__ uint64_t eval_digits(const uint64_t *v, const uint64_
 // the K residues mod p_k of the centred integer (x - Q when x >= (Q + 1) / 2)
 template <int L, int K>
 __global__ __launch_bounds__(256) void k_rns_extend(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
-                                                    const RnsConv *__restrict__ cv, uint32_t N) {
+                                                    const RnsConv *__restrict__ cv, uint32_t N, uint32_t sh) {
   constexpr int E = L + K;
-  const uint32_t k = blockIdx.x * 256u + threadIdx.x;
-  if (k >= N) return;
-  const uint32_t poly = blockIdx.y;
+  const uint32_t k = ((blockIdx.x & ((1u << sh) - 1u)) << 8) + threadIdx.x;
+  const uint32_t poly = blockIdx.x >> sh;
   const uint64_t *src = in + (size_t)poly * L * N + k;
   uint64_t *dst = out + (size_t)poly * E * N + k;
   uint64_t x[L], v[L];
@@ -98,12 +98,12 @@ __global__ __launch_bounds__(256) void k_rns_extend(uint64_t *__restrict__ out, 
 template <int L, int K>
 __global__ __launch_bounds__(256) void k_rns_scale_round(uint64_t *__restrict__ out, uint64_t *__restrict__ dig,
                                                          const uint64_t *__restrict__ X,
-                                                         const RnsConv *__restrict__ cv, uint32_t N) {
+                                                         const RnsConv *__restrict__ cv, uint32_t N, uint32_t sh) {
   constexpr int E = L + K;
-  const uint32_t k = blockIdx.x * 256u + threadIdx.x;
-  if (k >= N) return;
-  const uint32_t o = blockIdx.y / 3, slot = blockIdx.y % 3;
-  const uint64_t *src = X + (size_t)blockIdx.y * E * N + k;
+  const uint32_t k = ((blockIdx.x & ((1u << sh) - 1u)) << 8) + threadIdx.x;
+  const uint32_t row = blockIdx.x >> sh;   // o * 3 + slot
+  const uint32_t o = row / 3, slot = row % 3;
+  const uint64_t *src = X + (size_t)row * E * N + k;
   uint64_t r[L], v[L], z[K], w[K];
 #pragma unroll
   for (int i = 0; i < L; ++i) r[i] = mulc(src[(size_t)i * N], cv->t_q[i], cv->t_qs[i], cv->q[i]);   // (t x) mod q_i
@@ -138,11 +138,13 @@ __global__ __launch_bounds__(256) void k_rns_scale_round(uint64_t *__restrict__ 
 template <int L, int K>
 hipError_t launch_lk(const RnsConv *d_conv, uint64_t *out, uint64_t *dig, const uint64_t *in, uint32_t rows, uint32_t N,
                      bool extend, hipStream_t st) {
-  const dim3 grid((N + 255) / 256, rows);
+  // 256 coefficients per block, rows along x (N is a power of two >= 1024)
+  const uint32_t sh = (uint32_t)__builtin_ctz(N) - 8;
+  const dim3 grid(rows << sh);
   if (extend)
-    hipLaunchKernelGGL((k_rns_extend<L, K>), grid, dim3(256), 0, st, out, in, d_conv, N);
+    hipLaunchKernelGGL((k_rns_extend<L, K>), grid, dim3(256), 0, st, out, in, d_conv, N, sh);
   else
-    hipLaunchKernelGGL((k_rns_scale_round<L, K>), grid, dim3(256), 0, st, out, dig, in, d_conv, N);
+    hipLaunchKernelGGL((k_rns_scale_round<L, K>), grid, dim3(256), 0, st, out, dig, in, d_conv, N, sh);
   return hipGetLastError();
 }
 

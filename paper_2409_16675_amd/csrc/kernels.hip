@@ -70,11 +70,12 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
 
 // Component 1 of ciphertexts first .. first+n-1 regenerated from the seed,
 // written [n][L][N] (coefficient form).
+// one 256-thread block per 256 coefficients of a plane: block b covers plane
+// b >> sh, coefficients ((b & (2^sh - 1)) << 8) + threadIdx.x (sh = log2 N - 8)
 __global__ void k_expand_c1(uint64_t *__restrict__ out, const PrimeK *__restrict__ primes, int L, int N, Seed seed,
-                            uint32_t first) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (uint32_t)N) return;
-  const uint32_t p = blockIdx.y;   // jj * L + i
+                            uint32_t first, uint32_t sh) {
+  const uint32_t k = ((blockIdx.x & ((1u << sh) - 1u)) << 8) + threadIdx.x;
+  const uint32_t p = blockIdx.x >> sh;   // jj * L + i
   const uint32_t i = p % (uint32_t)L, jj = p / (uint32_t)L;
   out[(size_t)p * N + k] = c1_residue(seed, first + jj, i, k, primes[i]);
 }
@@ -191,9 +192,9 @@ template <class A>
 __global__ __launch_bounds__(256) void k_mac_slots(uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat,
                                                    const uint64_t *__restrict__ pt_hat, TermArgs ta,
                                                    const PrimeK *__restrict__ primes, int L, int N, int accumulate) {
-  const int plane = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
+  const int sh = __builtin_ctz((unsigned)N) - 8;           // blocks of 256 per plane: 2^sh
+  const int plane = (int)(blockIdx.x >> sh);
+  const int k = (int)(((blockIdx.x & ((1u << sh) - 1u)) << 8) + threadIdx.x);
   const int i = plane % L;
   const int comp = (plane / L) & 1;
   const int o = plane / (2 * L);
@@ -498,9 +499,9 @@ hipError_t launch_ntt_fwd_seeded(const Ctx &c, const Sched &s, uint64_t *out, co
 hipError_t launch_expand_c1(const Ctx &c, uint64_t *out, uint64_t seed0, uint64_t seed1, uint32_t first, uint32_t n_ct,
                             hipStream_t st) {
   if (!n_ct) return hipSuccess;
-  dim3 grid((c.N + 255) / 256, n_ct * c.L);
-  hipLaunchKernelGGL(k_expand_c1, grid, dim3(256), 0, st, out, c.d_primes, (int)c.L, (int)c.N, Seed{seed0, seed1},
-                     first);
+  const uint32_t sh = c.logN - 8;
+  hipLaunchKernelGGL(k_expand_c1, dim3((n_ct * c.L) << sh), dim3(256), 0, st, out, c.d_primes, (int)c.L, (int)c.N,
+                     Seed{seed0, seed1}, first, sh);
   return hipGetLastError();
 }
 
@@ -530,7 +531,7 @@ hipError_t launch_mac(const Ctx &c, const Sched &s, uint64_t *out, const uint64_
   if (ncomp == 1 && (out_ntt || accumulate)) return hipErrorInvalidValue;
   if (n_planes == 0) return hipSuccess;
   if (out_ntt) {
-    dim3 grid((c.N + 255) / 256, n_planes);
+    const dim3 grid(n_planes << (c.logN - 8));   // 256 coefficients per block, planes along x
     if (s.arith == HE_ARITH_F64 && c.f64_ok)
       hipLaunchKernelGGL(k_mac_slots<ArF64>, grid, dim3(256), 0, st, out, ct_hat, pt_hat, ta, c.d_primes, (int)c.L,
                          (int)c.N, accumulate ? 1 : 0);
