@@ -24,9 +24,9 @@
 #include "rns.hpp"
 
 namespace he {
-hipError_t launch_rns_extend(const RnsConv *d_conv, int L, int K, uint64_t *out, const uint64_t *in,
+hipError_t launch_rns_extend(const RnsConv *d_conv, int L, int K, bool f64, uint64_t *out, const uint64_t *in,
                              uint32_t n_polys, uint32_t N, hipStream_t st);
-hipError_t launch_rns_scale_round(const RnsConv *d_conv, int L, int K, uint64_t *out, uint64_t *dig,
+hipError_t launch_rns_scale_round(const RnsConv *d_conv, int L, int K, bool f64, uint64_t *out, uint64_t *dig,
                                   const uint64_t *X, uint32_t n_out, uint32_t N, hipStream_t st);
 
 namespace {
@@ -113,6 +113,25 @@ void fill_conv(RnsConv &cv, const std::vector<uint64_t> &q, const std::vector<ui
   host_mrc(h, cv.hq, L, q.data());
   for (int k = 0; k < K; ++k) h[k] = (p[k] + 1) / 2;
   host_mrc(h, cv.hp, K, p.data());
+  for (int i = 0; i < kRnsMax; ++i) {
+    cv.dq[i] = (double)cv.q[i];
+    cv.dqinv[i] = i < L ? 1.0 / (double)q[i] : 0.0;
+    cv.dp[i] = (double)cv.p[i];
+    cv.dpinv[i] = i < K ? 1.0 / (double)p[i] : 0.0;
+    cv.dt_q[i] = (double)cv.t_q[i];
+    cv.dt_p[i] = (double)cv.t_p[i];
+    cv.dqinv_p[i] = (double)cv.qinv_p[i];
+    cv.dq_mod_p[i] = (double)cv.q_mod_p[i];
+    cv.dp_mod_q[i] = (double)cv.p_mod_q[i];
+    cv.dhq[i] = (double)cv.hq[i];
+    cv.dhp[i] = (double)cv.hp[i];
+    for (int j = 0; j < kRnsMax; ++j) {
+      cv.diqq[i][j] = (double)cv.iqq[i][j];
+      cv.dipp[i][j] = (double)cv.ipp[i][j];
+      cv.dwq[i][j] = (double)cv.wq[i][j];
+      cv.dwp[i][j] = (double)cv.wp[i][j];
+    }
+  }
 }
 
 he_status ext_ring(Ctx &c, Ctx **ec, const RnsConv **conv) {
@@ -320,9 +339,9 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
   uint64_t *X = (uint64_t *)(w + l.x), *dig = (uint64_t *)(w + l.dig);
   const Sched sf{ec->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64, c.s_fwd.loge};
   const Sched sm{ec->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64, c.s_mac.loge};
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), stage, a, n_a * 2, N, st); }), "ccmul extend a");
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), ec->f64_ok, stage, a, n_a * 2, N, st); }), "ccmul extend a");
   HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*ec, sf, a_hat, stage, n_a * 2 * E, st); }), "ccmul fwd a");
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), stage, b, n_b * 2, N, st); }), "ccmul extend b");
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), ec->f64_ok, stage, b, n_b * 2, N, st); }), "ccmul extend b");
   HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*ec, sf, b_hat, stage, n_b * 2 * E, st); }), "ccmul fwd b");
   Terms tt;
   tt.row = d_tl + t_row;
@@ -331,7 +350,7 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
   tt.n_out = n_out * 3;
   HIPCHK(timed(c, st, KK_MAC_INV, [&] { return launch_mac(*ec, sm, X, a_hat, b_hat, tt, false, false, st, 1); }),
          "ccmul tensor");
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_scale_round(cv, (int)L, (int)(E - L), out, dig, X, n_out, N, st); }),
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_scale_round(cv, (int)L, (int)(E - L), ec->f64_ok, out, dig, X, n_out, N, st); }),
          "ccmul scale and round");
   HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, X, dig, n_out * L * L, st); }),
          "ccmul fwd digits");

@@ -31,6 +31,12 @@ struct RnsConv {
   uint64_t ipp[kRnsMax][kRnsMax], ipps[kRnsMax][kRnsMax];   // [j][k]: p_j^-1 mod p_k (j < k)
   uint64_t wq[kRnsMax][kRnsMax], wqs[kRnsMax][kRnsMax];     // [i][k]: prod_{j<i} q_j mod p_k
   uint64_t wp[kRnsMax][kRnsMax], wps[kRnsMax][kRnsMax];     // [k][i]: prod_{j<k} p_j mod q_i
+  // the same values as doubles (exact when every prime is below 2^50, the
+  // condition under which the fp64 products are used), and 1 / prime
+  double dq[kRnsMax], dqinv[kRnsMax], dp[kRnsMax], dpinv[kRnsMax];
+  double dt_q[kRnsMax], dt_p[kRnsMax], dqinv_p[kRnsMax], dq_mod_p[kRnsMax], dp_mod_q[kRnsMax];
+  double dhq[kRnsMax], dhp[kRnsMax];
+  double diqq[kRnsMax][kRnsMax], dipp[kRnsMax][kRnsMax], dwq[kRnsMax][kRnsMax], dwp[kRnsMax][kRnsMax];
 };
 
 }  // namespace he
