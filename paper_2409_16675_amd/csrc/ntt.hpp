@@ -12,7 +12,7 @@
 // stage S0 and R stages the index bits are [S0 high bits | R pass bits | rest]
 // and each thread owns whole radix-2^R groups (the pass bits live in the
 // register index), so a pass needs no communication; between passes the
-// plane goes through LDS (padded by one word every 32 to spread banks).  The
+// plane goes through LDS (padded by one word every 16 to spread banks).  The
 // first forward pass reads HBM directly and the last inverse pass writes HBM
 // directly: in both the thread index maps to the low index bits, so those
 // accesses are coalesced.  The bit-reversed side goes through LDS.
@@ -21,6 +21,8 @@
 
 namespace he {
 
+constexpr int kLdsPadShift = 4;
+
 template <int LOGN_, int LOGT_>
 struct Geo {
   static constexpr int LOGN = LOGN_, LOGT = LOGT_;
@@ -28,13 +30,20 @@ struct Geo {
   static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
   static constexpr int s0(int k) { return k * LOGE; }
   static constexpr int r(int k) { return (LOGN - k * LOGE) < LOGE ? (LOGN - k * LOGE) : LOGE; }
-  static constexpr int LDS_WORDS = N + (N >> 5);
+  static constexpr int LDS_WORDS = N + (N >> kLdsPadShift);
 };
 
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lpad_c(int i) { return i + (i >> 5); }
-// LDS word of linear index j * NT + tid (tid < NT, NT a multiple of 32): the
-// two parts have disjoint bits, so the padding splits (see pass_index).
+// LDS words of a plane are padded by one word after every 2^kLdsPadShift.
+// LDS serves 16 lanes of a 64-bit access per clock over 32 four-byte banks;
+// with 16 coefficients per thread every pass's pattern (a stride of 1, of 2,
+// or of 32 words at the lane bits that leave the low index bits) then spreads
+// over all 32 banks, where a pad every 32 words left two of the four passes
+// 2-way conflicted (the measured conflict cycles of the transforms match that
+// count exactly).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> kLdsPadShift); }
+__host__ __device__ constexpr int lpad_c(int i) { return i + (i >> kLdsPadShift); }
+// LDS word of linear index j * NT + tid (tid < NT): the two parts have
+// disjoint bits, so the padding splits (see pass_index).
 template <class G>
 __device__ __forceinline__ int lin_lds(int tid, int j) {
   return lpad(tid) + lpad_c(j * G::NT);
@@ -69,7 +78,7 @@ __device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, uint32_t idx) {
 // keeps the register count low enough for that occupancy.
 template <int LOGN, int LOGT>
 struct MinWaves {
-  static constexpr int lds = ((1 << LOGN) + (1 << (LOGN - 5))) * 8 + 256;
+  static constexpr int lds = ((1 << LOGN) + (1 << (LOGN - kLdsPadShift))) * 8 + 256;
   static constexpr int wg = (163840 / lds) < 1 ? 1 : (163840 / lds);
   static constexpr int w = wg * (1 << LOGT) / 64 / 4;
   static constexpr int value = w < 1 ? 1 : (w > 8 ? 8 : w);

@@ -157,7 +157,7 @@ template <class A, int SLAB, int LOGE, int LOGN_MIN, int LOGN_MAX>
 struct PCfg {
   static_assert(LOGN_MIN - LOGE >= 6, "a plane group must hold whole waves");
   static constexpr int NT = 1 << (SLAB - LOGE);
-  static constexpr int LDS_BYTES = ((1 << SLAB) + (1 << (SLAB - 5))) * 8;
+  static constexpr int LDS_BYTES = ((1 << SLAB) + (1 << (SLAB - kLdsPadShift))) * 8;
   static constexpr int WG_PER_CU = (163840 / (LDS_BYTES + 512)) < 1 ? 1 : (163840 / (LDS_BYTES + 512));
   static constexpr int MINW = (WG_PER_CU * NT / 256) < 1 ? 1 : (WG_PER_CU * NT / 256 > 8 ? 8 : WG_PER_CU * NT / 256);
 };
@@ -249,7 +249,7 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     // group index is wave-uniform
     const int group = __builtin_amdgcn_readfirstlane(tid >> logt);
     const int tid_g = tid & ((1 << logt) - 1);
-    const int words = (1 << logn) + (1 << (logn - 5));
+    const int words = (1 << logn) + (1 << (logn - kLdsPadShift));
     typename A::V *lds_g = lds + (size_t)group * words;
     if constexpr (LOGN_MIN == LOGN_MAX) {
       run_task<A, LOGN_MIN, LOGE>(tk, jb, tid_g, group, lds_g);
@@ -327,7 +327,7 @@ bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pre
     v = PVariant{arith, 14, 4, 10, 14};
   }
   v.threads = 1 << (v.slab - v.loge);
-  v.lds_bytes = ((1 << v.slab) + (1 << (v.slab - 5))) * 8;
+  v.lds_bytes = ((1 << v.slab) + (1 << (v.slab - kLdsPadShift))) * 8;
   v.wg_per_cu = 163840 / (v.lds_bytes + 512);
   if (v.wg_per_cu < 1) v.wg_per_cu = 1;
   return true;
