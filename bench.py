@@ -38,13 +38,14 @@ OPS_MAC_TERM = OPS_MODMUL + 2   # quotient companion mul + accumulate add
 
 
 def kernel_src_sha():
-    """Digest of the device-code sources (the .hip kernels and the .hpp headers
-    they include): hardware byte counts below are reported only for the kernels
-    they were taken on; host-only .cpp files do not enter it."""
+    """Digest of the sources that decide the persistent launch's memory traffic:
+    the device code (the .hip kernels and the .hpp headers they include) and
+    batch.cpp, which lays out the launch's task queues.  Hardware byte counts
+    below are reported only for the sources they were taken on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2409_16675_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(x for x in os.listdir(d) if x.endswith((".hip", ".hpp"))):
+    for f in sorted(x for x in os.listdir(d) if x.endswith((".hip", ".hpp")) or x == "batch.cpp"):
         h.update(f.encode())
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())

@@ -137,9 +137,17 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
   const uint32_t n_pre = (uint32_t)tasks.size();
   for (size_t j = 0; j < nj; ++j) {
     const JobRef &bj = jobs[j];
-    const uint32_t G = slab_n >> bj.ctx->logN;
-    const uint32_t planes = bj.plan->info.n_ct_out * 2 * bj.ctx->L;
-    for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
+    const uint32_t G = slab_n >> bj.ctx->logN, L = bj.ctx->L;
+    const uint32_t planes = bj.plan->info.n_ct_out * 2 * L;
+    if (G == 1) {
+      // one plane per task: prime-major order (plane (o * 2 + comp) * L + i
+      // for i, then o, then comp), so that the operands and twiddles an XCD
+      // works on at a time are those of one prime and stay in its L2
+      for (uint32_t i = 0; i < L; ++i)
+        for (uint32_t oc = 0; oc < planes / L; ++oc) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, oc * L + i, 1u});
+    } else {
+      for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
+    }
     info.inv_planes += planes;
   }
   // dependent tasks, in output order, cut into kXcds contiguous queues: outputs
