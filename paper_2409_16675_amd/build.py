@@ -13,7 +13,10 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhe.so")
 
-SOURCES = ["kernels.hip", "persistent.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp", "ccmul.hip", "ccmul.cpp"]
+# longest compiles first: the pool of workers starts them together
+SOURCES = ["persistent.hip", "ccmul.hip", "ring_13.hip", "ring_12.hip", "ring_11.hip", "ring_14.hip", "ring_10.hip",
+           "kernels.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp",
+           "ccmul.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-ffp-contract=off",
