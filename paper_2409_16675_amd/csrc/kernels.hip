@@ -1,9 +1,13 @@
-// gfx950 kernels of libhe.so: transforms, fused multiply-accumulate + inverse
-// transform, plaintext packing, and the small helpers used by encryption.
+// gfx950 kernels of libhe.so outside the per-degree ring kernels: their launch
+// dispatch (the templates are in ring_kernels.hpp, instantiated by
+// ring_<log2 N>.hip), the multiply-accumulate left in the transformed domain,
+// plaintext packing, and the small helpers used by encryption.
 #include "ring_kernels.hpp"
 
 namespace he {
 
+// Component 1 of ciphertexts first .. first+n-1 regenerated from the seed,
+// written [n][L][N] (coefficient form).
 // one 256-thread block per 256 coefficients of a plane: block b covers plane
 // b >> sh, coefficients ((b & (2^sh - 1)) << 8) + threadIdx.x (sh = log2 N - 8)
 __global__ void k_expand_c1(uint64_t *__restrict__ out, const PrimeK *__restrict__ primes, int L, int N, Seed seed,

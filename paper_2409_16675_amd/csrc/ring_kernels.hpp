@@ -71,8 +71,6 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   }
 }
 
-// Component 1 of ciphertexts first .. first+n-1 regenerated from the seed,
-// written [n][L][N] (coefficient form).
 // Forward transform of signed integer polynomials lifted to every prime:
 // plane p reads polynomial p / L and lifts it modulo q_{p % L}.
 template <class A, int LOGN, int LOGT>
