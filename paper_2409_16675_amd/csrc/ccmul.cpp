@@ -8,9 +8,11 @@
 //      and fused inverse transform of the layer path (one component per
 //      operand; the three slots are term lists of their own);
 //   3. d = round(t x / Q) mod Q exactly (mixed-radix conversions, no floating
-//      point), slot 2 written as its RNS digits D_j = d2 mod q_j;
-//   4. relinearize: transform the digits and multiply-accumulate them against
-//      the key, accumulating into (d0, d1), with the same fused kernel.
+//      point); the residue of d2 mod q_j is the digit D_j;
+//   4. relinearize: transform every digit at every prime (the forward
+//      transform that lifts integer polynomials on load, reading D_j and
+//      reducing it mod q_i) and multiply-accumulate them against the key,
+//      accumulating into (d0, d1), with the same fused kernel.
 // P is sized so that every tensor value and every quotient z = (t x - r) / Q
 // is exact in it: log2 P >= log2 t + log2 N + 16 + log2 Q + 2 (up to 2^16
 // products per output).
@@ -216,7 +218,7 @@ CcLayout layout(const Ctx &c, uint32_t E, uint32_t n_a, uint32_t n_b, uint32_t n
   l.b_hat = take((size_t)n_b * 2 * E * plane);
   const size_t xb = (size_t)n_out * 3 * E * plane, db = (size_t)n_out * L * L * plane;
   l.x = take(xb > db ? xb : db);                       // tensor slots, then the transformed digits
-  l.dig = take(db);
+  l.dig = take((size_t)n_out * L * plane);             // d2: digit j is its residue mod q_j
   l.terms = take(4 * ((3 * (size_t)n_out + 1) + 8 * (size_t)n_terms + ((size_t)n_out + 1) + 2 * (size_t)n_out * L));
   l.flag = take((flags & HE_VALIDATE) ? 256 : 0);
   l.total = off;
@@ -352,7 +354,9 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
          "ccmul tensor");
   HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_scale_round(cv, (int)L, (int)(E - L), ec->f64_ok, out, dig, X, n_out, N, st); }),
          "ccmul scale and round");
-  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, X, dig, n_out * L * L, st); }),
+  // plane (o * L + j) * L + i of the transformed digits: d2[o][j] lifted mod q_i
+  HIPCHK(timed(c, st, KK_FWD_LIFT,
+               [&] { return launch_ntt_fwd_lift(c, c.s_fwd, X, (const int64_t *)dig, n_out * L, st); }),
          "ccmul fwd digits");
   Terms tr;
   tr.row = d_tl + r_row;

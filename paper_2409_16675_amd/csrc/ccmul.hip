@@ -162,8 +162,8 @@ __global__ __launch_bounds__(256) void k_rns_extend(uint64_t *__restrict__ out, 
 // X [n][3][L+K][N]: the tensor slots as integers |x| < QP / 2 (centred in Q u P).
 // For each slot d = round(t x / Q) mod Q: with y = t x and r = y mod Q in [0, Q),
 // z = (y - r) / Q is exact in P (|z| < P / 2), and d = z + [r >= (Q + 1) / 2].
-// Slots 0 and 1 go to out [n][2][L][N]; slot 2 to the digits
-// dig [n][L][L][N], dig[o][j][i] = (d mod q_j) mod q_i.
+// Slots 0 and 1 go to out [n][2][L][N], slot 2 to dig [n][L][N]: its residue
+// mod q_j is the relinearization digit D_j (an integer in [0, q_j)).
 template <class R, int L, int K>
 __global__ __launch_bounds__(256) void k_rns_scale_round(uint64_t *__restrict__ out, uint64_t *__restrict__ dig,
                                                          const uint64_t *__restrict__ X,
@@ -197,13 +197,8 @@ __global__ __launch_bounds__(256) void k_rns_scale_round(uint64_t *__restrict__ 
     V d = eval_digits<R, K, true>(w, cv, i, qi);
     if (neg) d = R::sub(d, R::ld(cv->p_mod_q[i]), qi);
     if (up) d = R::add(d, V(1), qi);
-    if (slot < 2) {
-      out[((size_t)(o * 2 + slot) * L + i) * N + k] = R::st(d);
-    } else {
-      uint64_t *dd = dig + ((size_t)(o * L + i) * L) * N + k;
-#pragma unroll
-      for (int i2 = 0; i2 < L; ++i2) dd[(size_t)i2 * N] = R::st(R::red(d, mod_q(cv, i2)));
-    }
+    if (slot < 2) out[((size_t)(o * 2 + slot) * L + i) * N + k] = R::st(d);
+    else dig[((size_t)o * L + i) * N + k] = R::st(d);
   }
 }
 
