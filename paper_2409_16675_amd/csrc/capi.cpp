@@ -455,9 +455,35 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
     HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, st); }), "conv fwd ct");
     ct_hat = d;
   }
-  // 2. pack (raw weights) and transform the plaintexts
+  // 2. pack (raw weights) and transform the plaintexts: fused in one kernel
+  // (packing in LDS), or packed to memory first on the unfused path
+  uint64_t *pt_hat = (uint64_t *)(w + L.pt_hat);
+  const bool pack_fused = !(flags & (HE_PLAIN_POLY | HE_UNFUSED));
+  if (pack_fused) {
+    WPack wp{};
+    if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX) {
+      wp.kind = in.kind == HE_KIND_DX ? WP_CONV_DX : WP_CONV;
+      wp.M = p.eq.M;
+      wp.C = p.eq.C;
+      wp.h = p.eq.h;
+      wp.O = in.O;
+      wp.S = in.S;
+      wp.Cw = in.Cw;
+      wp.cb = in.cb;
+    } else {
+      wp.kind = WP_FC;
+      wp.n_out = p.shape.n_out;
+      wp.n_in = p.shape.n_in;
+      wp.n_iw = in.n_iw;
+      wp.n_ow = in.n_ow;
+      wp.in_ct = (p.shape.n_in + in.n_iw - 1) / in.n_iw;
+    }
+    HIPCHK(timed(c, st, KK_FWD_LIFT,
+                 [&] { return launch_ntt_fwd_pack(c, c.s_fwd, pt_hat, (const int32_t *)plain, wp, in.n_pt, st); }),
+           "conv pack + fwd pt");
+  }
   const int64_t *polys = (const int64_t *)plain;
-  if (!(flags & HE_PLAIN_POLY)) {
+  if (!pack_fused && !(flags & HE_PLAIN_POLY)) {
     int64_t *pp = (int64_t *)(w + L.pt_poly);
     HIPCHK(timed(c, st, KK_PACK, [&] {
              hipError_t e = launch_zero_i64(pp, (size_t)in.n_pt * c.N, st);
@@ -471,8 +497,9 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
            "pack");
     polys = pp;
   }
-  uint64_t *pt_hat = (uint64_t *)(w + L.pt_hat);
-  HIPCHK(timed(c, st, KK_FWD_LIFT, [&] { return launch_ntt_fwd_lift(c, c.s_fwd, pt_hat, polys, in.n_pt, st); }), "conv fwd pt");
+  if (!pack_fused)
+    HIPCHK(timed(c, st, KK_FWD_LIFT, [&] { return launch_ntt_fwd_lift(c, c.s_fwd, pt_hat, polys, in.n_pt, st); }),
+           "conv fwd pt");
   // 3. multiply-accumulate + inverse transform
   Terms tm;
   tm.row = p.d_row();

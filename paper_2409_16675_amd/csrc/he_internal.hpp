@@ -93,6 +93,17 @@ hipError_t launch_ntt_fwd_lift(const Ctx &c, const Sched &s, uint64_t *out, cons
                                hipStream_t st);
 hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
                           hipStream_t st);
+// Layout of raw weights packed into plaintext polynomials (pack.hpp scatters them).
+enum WPackKind : uint32_t { WP_CONV = 0, WP_CONV_DX = 1, WP_FC = 2 };
+struct WPack {
+  uint32_t kind;                               // WP_*
+  uint32_t M, C, h, O, S, Cw, cb;              // conv (DX: of the equivalent forward conv)
+  uint32_t n_out, n_in, n_iw, n_ow, in_ct;     // FC
+};
+// forward transform of n_polys plaintext polynomials packed from raw int32
+// weights in LDS (layout wp): out [n_polys][L][N]
+hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, const int32_t *w, const WPack &wp,
+                               uint32_t n_polys, hipStream_t st);
 // forward transform of n_ct ciphertexts [n_ct][2][L][N] whose component 0 is ct0
 // [n_ct][L][N] and whose component 1 is regenerated from the seed
 hipError_t launch_ntt_fwd_seeded(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct0, uint64_t seed0,

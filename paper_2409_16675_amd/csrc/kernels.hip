@@ -238,6 +238,16 @@ hipError_t launch_ntt_fwd_lift(const Ctx &c, const Sched &s, uint64_t *out, cons
   return dispatch(c, s, OP_FWD_LIFT, la, st);
 }
 
+hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, const int32_t *w, const WPack &wp,
+                               uint32_t n_polys, hipStream_t st) {
+  LaunchArgs la{};
+  la.out = out;
+  la.polys = (const int64_t *)w;
+  la.wp = wp;
+  la.grid = n_polys * c.L;
+  return dispatch(c, s, OP_FWD_PACK, la, st);
+}
+
 hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
                           hipStream_t st) {
   LaunchArgs la{};

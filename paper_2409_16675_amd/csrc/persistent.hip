@@ -23,6 +23,7 @@
 #include "batch.hpp"
 #include "ntt.hpp"
 #include "mac.hpp"
+#include "pack.hpp"
 
 namespace he {
 
@@ -73,34 +74,10 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
 #pragma unroll
       for (int j = 0; j < G::E; ++j) lds_g[lin_lds<G>(tid_g, j)] = ar.load(0ull);
       __syncthreads();
-      const HE_GLOBAL int32_t *w = as_global((const int32_t *)jb.plain);
       if (valid) {
-        if (jb.pkind == PK_CONV || jb.pkind == PK_CONV_DX) {
-          const uint32_t m = pp / jb.cb, blk = pp % jb.cb, hh = jb.h * jb.h;
-          const uint32_t c0 = blk * jb.Cw, c1 = min(jb.C, c0 + jb.Cw);
-          const uint32_t n = (c1 - c0) * hh;
-          const bool dx = jb.pkind == PK_CONV_DX;
-          for (uint32_t id = tid_g; id < n; id += G::NT) {
-            const uint32_t cc = id / hh, ab = id % hh, a = ab / jb.h, b = ab % jb.h;
-            // input gradient: forward weights [C][M][h][h], transposed and rotated
-            const size_t src = dx ? (((size_t)(c0 + cc) * jb.M + m) * jb.h + (jb.h - 1 - a)) * jb.h + (jb.h - 1 - b)
-                                  : ((size_t)m * jb.C + c0 + cc) * hh + ab;
-            const int64_t v = w[src];
-            const uint32_t pos = (jb.h - 1 - a) * jb.O + (jb.h - 1 - b);
-            if (cc == 0) lds_g[lpad(pos)] = ar.load_signed(v);
-            else lds_g[lpad(G::N - cc * jb.S + pos)] = ar.load_signed(-v);
-          }
-        } else {   // PK_FC: poly (ko, ki) holds W[ko*n_ow + ii][ki*n_iw + jj] at ii*n_iw + n_iw-1-jj
-          const uint32_t ko = pp / jb.in_ct, ki = pp % jb.in_ct;
-          const uint32_t i0 = ko * jb.n_ow, i1 = min(jb.n_out, i0 + jb.n_ow);
-          const uint32_t j0 = ki * jb.n_iw, j1 = min(jb.n_in, j0 + jb.n_iw);
-          const uint32_t wi = j1 - j0, n = (i1 - i0) * wi;
-          for (uint32_t id = tid_g; id < n; id += G::NT) {
-            const uint32_t ii = id / wi, jj = id % wi;
-            const int64_t v = w[(size_t)(i0 + ii) * jb.n_in + j0 + jj];
-            lds_g[lpad(ii * jb.n_iw + jb.n_iw - 1 - jj)] = ar.load_signed(v);
-          }
-        }
+        const WPack wp{jb.pkind == PK_CONV ? (uint32_t)WP_CONV : (jb.pkind == PK_CONV_DX ? (uint32_t)WP_CONV_DX : (uint32_t)WP_FC),
+                       jb.M, jb.C, jb.h, jb.O, jb.S, jb.Cw, jb.cb, jb.n_out, jb.n_in, jb.n_iw, jb.n_ow, jb.in_ct};
+        scatter_weights<A, G>(ar, lds_g, tid_g, wp, pp, as_global((const int32_t *)jb.plain));
       }
       __syncthreads();
       ntt_forward_tc<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, LdsAt<typename A::V>{lds_g}, st);

@@ -9,6 +9,7 @@
 #include "ntt.hpp"
 #include "mac.hpp"
 #include "prng.hpp"
+#include "pack.hpp"
 
 namespace he {
 
@@ -90,6 +91,31 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   auto ld = [&](int k) { return ar.load_signed(src[(uint32_t)k]); };
   auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
   ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+}
+
+// Forward transform of plaintext polynomials packed from raw weights in LDS:
+// plane p is polynomial p / L at prime p % L; the workgroup zeroes the plane,
+// scatters the polynomial's weights and transforms it from LDS (no packed
+// polynomial in HBM).
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd_pack(
+    uint64_t *__restrict__ out, WPack wp, const int32_t *__restrict__ w, const PrimeK *__restrict__ primes,
+    const typename A::Tw *__restrict__ tw, int L) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int plane = blockIdx.x;
+  const int i = plane % L;
+  const A ar(primes[i]);
+  uint64_t *dst = out + (size_t)plane * G::N;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = ar.load(0ull);
+  __syncthreads();
+  scatter_weights<A, G>(ar, lds, tid, wp, (uint32_t)(plane / L), w);
+  __syncthreads();
+  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+  ntt_forward_tc<A, G>(ar, tw + (size_t)i * G::N, tid, lds, LdsAt<typename A::V>{lds}, st);
 }
 
 template <class A, int LOGN, int LOGT>
@@ -201,7 +227,7 @@ inline const TwU64 *tw_ptr<ArU64>(const Ctx &c, bool inverse) {
   return (const TwU64 *)(inverse ? c.d_tw_u64_inv : c.d_tw_u64_fwd);
 }
 
-enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED };
+enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED, OP_FWD_PACK };
 
 struct LaunchArgs {
   uint64_t *out;
@@ -212,6 +238,7 @@ struct LaunchArgs {
   int accumulate;
   int ncomp;
   Seed seed;
+  WPack wp;       // OP_FWD_PACK: layout of the weights (polys: the int32 weights)
   unsigned grid;
 };
 
@@ -235,6 +262,11 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
       if ((e = prep(k_ntt_fwd_seeded<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
       hipLaunchKernelGGL((k_ntt_fwd_seeded<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in,
                          c.d_primes, tw_ptr<A>(c, false), (int)c.L, la.seed);
+      break;
+    case OP_FWD_PACK:
+      if ((e = prep(k_ntt_fwd_pack<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_fwd_pack<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.wp,
+                         (const int32_t *)la.polys, c.d_primes, tw_ptr<A>(c, false), (int)c.L);
       break;
     case OP_INV:
       if ((e = prep(k_ntt_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
