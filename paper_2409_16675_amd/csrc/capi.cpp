@@ -443,8 +443,35 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
   }
   if ((flags & HE_PLAIN_POLY) == 0 && in.kind == HE_KIND_DW)
     return fail(HE_EUNSUPPORTED, "weight-gradient plaintexts are passed as packed polynomials (HE_PLAIN_POLY)");
-  // 1. transform the input ciphertexts
+  // weights packed in LDS inside the plaintext transform (fused path), or
+  // packed to memory first (unfused baseline, or polynomials given)
+  uint64_t *pt_hat = (uint64_t *)(w + L.pt_hat);
+  const bool pack_fused = !(flags & (HE_PLAIN_POLY | HE_UNFUSED));
+  WPack wp{};
+  if (!pack_fused) {
+    // weight-gradient layers (polynomials given) and the unfused baseline pack
+    // nothing here; the layout below is for raw conv, input-gradient or FC weights
+  } else if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX) {
+    wp.kind = in.kind == HE_KIND_DX ? WP_CONV_DX : WP_CONV;
+    wp.M = p.eq.M;
+    wp.C = p.eq.C;
+    wp.h = p.eq.h;
+    wp.O = in.O;
+    wp.S = in.S;
+    wp.Cw = in.Cw;
+    wp.cb = in.cb;
+  } else if (in.kind == HE_KIND_FC) {
+    wp.kind = WP_FC;
+    wp.n_out = p.shape.n_out;
+    wp.n_in = p.shape.n_in;
+    wp.n_iw = in.n_iw;
+    wp.n_ow = in.n_ow;
+    wp.in_ct = (p.shape.n_in + in.n_iw - 1) / in.n_iw;
+  }
+  // 1. transform the input ciphertexts (2. and the packed plaintexts, in the
+  // same launch when both are transformed here)
   const uint64_t *ct_hat = ct_in;
+  bool pt_done = false;
   if (seed) {
     uint64_t *d = (uint64_t *)(w + L.ct_hat);
     HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd_seeded(c, c.s_fwd, d, ct_in, seed[0], seed[1], in.n_ct_in, st); }),
@@ -452,36 +479,24 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
     ct_hat = d;
   } else if (!(flags & HE_IN_NTT)) {
     uint64_t *d = (uint64_t *)(w + L.ct_hat);
-    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, st); }), "conv fwd ct");
+    if (pack_fused) {
+      HIPCHK(timed(c, st, KK_FWD, [&] {
+               return launch_ntt_fwd_ct_pack(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, pt_hat, (const int32_t *)plain,
+                                             wp, in.n_pt, st);
+             }),
+             "conv fwd ct + pack fwd pt");
+      pt_done = true;
+    } else {
+      HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, st); }),
+             "conv fwd ct");
+    }
     ct_hat = d;
   }
-  // 2. pack (raw weights) and transform the plaintexts: fused in one kernel
-  // (packing in LDS), or packed to memory first on the unfused path
-  uint64_t *pt_hat = (uint64_t *)(w + L.pt_hat);
-  const bool pack_fused = !(flags & (HE_PLAIN_POLY | HE_UNFUSED));
-  if (pack_fused) {
-    WPack wp{};
-    if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX) {
-      wp.kind = in.kind == HE_KIND_DX ? WP_CONV_DX : WP_CONV;
-      wp.M = p.eq.M;
-      wp.C = p.eq.C;
-      wp.h = p.eq.h;
-      wp.O = in.O;
-      wp.S = in.S;
-      wp.Cw = in.Cw;
-      wp.cb = in.cb;
-    } else {
-      wp.kind = WP_FC;
-      wp.n_out = p.shape.n_out;
-      wp.n_in = p.shape.n_in;
-      wp.n_iw = in.n_iw;
-      wp.n_ow = in.n_ow;
-      wp.in_ct = (p.shape.n_in + in.n_iw - 1) / in.n_iw;
-    }
+  // 2. pack (raw weights) and transform the plaintexts
+  if (pack_fused && !pt_done)
     HIPCHK(timed(c, st, KK_FWD_LIFT,
                  [&] { return launch_ntt_fwd_pack(c, c.s_fwd, pt_hat, (const int32_t *)plain, wp, in.n_pt, st); }),
            "conv pack + fwd pt");
-  }
   const int64_t *polys = (const int64_t *)plain;
   if (!pack_fused && !(flags & HE_PLAIN_POLY)) {
     int64_t *pp = (int64_t *)(w + L.pt_poly);

@@ -248,6 +248,20 @@ hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, cons
   return dispatch(c, s, OP_FWD_PACK, la, st);
 }
 
+hipError_t launch_ntt_fwd_ct_pack(const Ctx &c, const Sched &s, uint64_t *ct_out, const uint64_t *ct_in,
+                                  uint32_t n_ct_planes, uint64_t *pt_out, const int32_t *w, const WPack &wp,
+                                  uint32_t n_polys, hipStream_t st) {
+  LaunchArgs la{};
+  la.out = ct_out;
+  la.in = ct_in;
+  la.n_first = (int)n_ct_planes;
+  la.out2 = pt_out;
+  la.polys = (const int64_t *)w;
+  la.wp = wp;
+  la.grid = n_ct_planes + n_polys * c.L;
+  return dispatch(c, s, OP_FWD_CT_PACK, la, st);
+}
+
 hipError_t launch_ntt_inv(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *in, uint32_t n_planes,
                           hipStream_t st) {
   LaunchArgs la{};

@@ -118,6 +118,43 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   ntt_forward_tc<A, G>(ar, tw + (size_t)i * G::N, tid, lds, LdsAt<typename A::V>{lds}, st);
 }
 
+// One launch for both operand sets of a layer: workgroups below n_ct_planes
+// transform input ciphertext planes (as k_ntt_fwd), the others pack and
+// transform plaintext planes from raw weights (as k_ntt_fwd_pack), so the two
+// small sets run concurrently instead of one after the other.
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd_ct_pack(
+    uint64_t *__restrict__ ct_out, const uint64_t *__restrict__ ct_in, int n_ct_planes, uint64_t *__restrict__ pt_out,
+    WPack wp, const int32_t *__restrict__ w, const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw,
+    int L) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x < n_ct_planes) {
+    const int plane = blockIdx.x;
+    const int i = plane % L;
+    const A ar(primes[i]);
+    const uint64_t *src = ct_in + (size_t)plane * G::N;
+    uint64_t *dst = ct_out + (size_t)plane * G::N;
+    auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+    auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+    ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+  } else {
+    const int plane = (int)blockIdx.x - n_ct_planes;
+    const int i = plane % L;
+    const A ar(primes[i]);
+    uint64_t *dst = pt_out + (size_t)plane * G::N;
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = ar.load(0ull);
+    __syncthreads();
+    scatter_weights<A, G>(ar, lds, tid, wp, (uint32_t)(plane / L), w);
+    __syncthreads();
+    auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+    ntt_forward_tc<A, G>(ar, tw + (size_t)i * G::N, tid, lds, LdsAt<typename A::V>{lds}, st);
+  }
+}
+
 template <class A, int LOGN, int LOGT>
 __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_inv(uint64_t *__restrict__ out, const uint64_t *__restrict__ in,
                                                        const PrimeK *__restrict__ primes,
@@ -227,7 +264,7 @@ inline const TwU64 *tw_ptr<ArU64>(const Ctx &c, bool inverse) {
   return (const TwU64 *)(inverse ? c.d_tw_u64_inv : c.d_tw_u64_fwd);
 }
 
-enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED, OP_FWD_PACK };
+enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED, OP_FWD_PACK, OP_FWD_CT_PACK };
 
 struct LaunchArgs {
   uint64_t *out;
@@ -238,7 +275,9 @@ struct LaunchArgs {
   int accumulate;
   int ncomp;
   Seed seed;
-  WPack wp;       // OP_FWD_PACK: layout of the weights (polys: the int32 weights)
+  WPack wp;       // OP_FWD_PACK, OP_FWD_CT_PACK: layout of the weights (polys: the int32 weights)
+  uint64_t *out2; // OP_FWD_CT_PACK: transformed plaintexts (out, in: the ciphertext planes)
+  int n_first;    // OP_FWD_CT_PACK: ciphertext planes (the first workgroups)
   unsigned grid;
 };
 
@@ -267,6 +306,12 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
       if ((e = prep(k_ntt_fwd_pack<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
       hipLaunchKernelGGL((k_ntt_fwd_pack<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.wp,
                          (const int32_t *)la.polys, c.d_primes, tw_ptr<A>(c, false), (int)c.L);
+      break;
+    case OP_FWD_CT_PACK:
+      if ((e = prep(k_ntt_fwd_ct_pack<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_fwd_ct_pack<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in,
+                         la.n_first, la.out2, la.wp, (const int32_t *)la.polys, c.d_primes, tw_ptr<A>(c, false),
+                         (int)c.L);
       break;
     case OP_INV:
       if ((e = prep(k_ntt_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
