@@ -474,8 +474,18 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
   bool pt_done = false;
   if (seed) {
     uint64_t *d = (uint64_t *)(w + L.ct_hat);
-    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd_seeded(c, c.s_fwd, d, ct_in, seed[0], seed[1], in.n_ct_in, st); }),
-           "conv fwd ct (seeded)");
+    if (pack_fused) {
+      HIPCHK(timed(c, st, KK_FWD, [&] {
+               return launch_ntt_fwd_ct_pack(c, c.s_fwd, d, ct_in, in.n_ct_in * 2 * c.L, pt_hat, (const int32_t *)plain,
+                                             wp, in.n_pt, st, seed);
+             }),
+             "conv fwd ct (seeded) + pack fwd pt");
+      pt_done = true;
+    } else {
+      HIPCHK(timed(c, st, KK_FWD,
+                   [&] { return launch_ntt_fwd_seeded(c, c.s_fwd, d, ct_in, seed[0], seed[1], in.n_ct_in, st); }),
+             "conv fwd ct (seeded)");
+    }
     ct_hat = d;
   } else if (!(flags & HE_IN_NTT)) {
     uint64_t *d = (uint64_t *)(w + L.ct_hat);

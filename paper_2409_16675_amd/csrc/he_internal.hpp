@@ -105,10 +105,12 @@ struct WPack {
 hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, const int32_t *w, const WPack &wp,
                                uint32_t n_polys, hipStream_t st);
 // both in one launch: n_ct_planes ciphertext planes ct_in -> ct_out, and
-// n_polys plaintext polynomials packed from w -> pt_out
+// n_polys plaintext polynomials packed from w -> pt_out.  With a seed
+// (2 words), ct_in holds component 0 only ([n][L][N]) and component 1 is
+// regenerated from the seed.
 hipError_t launch_ntt_fwd_ct_pack(const Ctx &c, const Sched &s, uint64_t *ct_out, const uint64_t *ct_in,
                                   uint32_t n_ct_planes, uint64_t *pt_out, const int32_t *w, const WPack &wp,
-                                  uint32_t n_polys, hipStream_t st);
+                                  uint32_t n_polys, hipStream_t st, const uint64_t *seed = nullptr);
 // forward transform of n_ct ciphertexts [n_ct][2][L][N] whose component 0 is ct0
 // [n_ct][L][N] and whose component 1 is regenerated from the seed
 hipError_t launch_ntt_fwd_seeded(const Ctx &c, const Sched &s, uint64_t *out, const uint64_t *ct0, uint64_t seed0,

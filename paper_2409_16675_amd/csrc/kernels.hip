@@ -250,8 +250,12 @@ hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, cons
 
 hipError_t launch_ntt_fwd_ct_pack(const Ctx &c, const Sched &s, uint64_t *ct_out, const uint64_t *ct_in,
                                   uint32_t n_ct_planes, uint64_t *pt_out, const int32_t *w, const WPack &wp,
-                                  uint32_t n_polys, hipStream_t st) {
+                                  uint32_t n_polys, hipStream_t st, const uint64_t *seed) {
   LaunchArgs la{};
+  if (seed) {
+    la.seeded = 1;
+    la.seed = Seed{seed[0], seed[1]};
+  }
   la.out = ct_out;
   la.in = ct_in;
   la.n_first = (int)n_ct_planes;

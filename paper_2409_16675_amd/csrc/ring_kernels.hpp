@@ -122,11 +122,13 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
 // transform input ciphertext planes (as k_ntt_fwd), the others pack and
 // transform plaintext planes from raw weights (as k_ntt_fwd_pack), so the two
 // small sets run concurrently instead of one after the other.
-template <class A, int LOGN, int LOGT>
+// SEEDED: the ciphertexts' component 1 is regenerated from the seed (plane
+// (j, comp, i): component 0 read from ct_in [n][L][N], as k_ntt_fwd_seeded).
+template <class A, int LOGN, int LOGT, bool SEEDED>
 __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd_ct_pack(
     uint64_t *__restrict__ ct_out, const uint64_t *__restrict__ ct_in, int n_ct_planes, uint64_t *__restrict__ pt_out,
     WPack wp, const int32_t *__restrict__ w, const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw,
-    int L) {
+    int L, Seed seed) {
   using G = Geo<LOGN, LOGT>;
   extern __shared__ __align__(16) unsigned char smem[];
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
@@ -134,12 +136,25 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   if ((int)blockIdx.x < n_ct_planes) {
     const int plane = blockIdx.x;
     const int i = plane % L;
-    const A ar(primes[i]);
-    const uint64_t *src = ct_in + (size_t)plane * G::N;
+    const PrimeK pk = primes[i];
+    const A ar(pk);
     uint64_t *dst = ct_out + (size_t)plane * G::N;
-    auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
     auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
-    ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+    if constexpr (SEEDED) {
+      const int comp = (plane / L) & 1, j = plane / (2 * L);
+      if (comp == 0) {
+        const uint64_t *src = ct_in + ((size_t)j * L + i) * G::N;
+        auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+        ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+      } else {
+        auto ld = [&](int k) { return ar.load(c1_residue(seed, (uint32_t)j, (uint32_t)i, (uint32_t)k, pk)); };
+        ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+      }
+    } else {
+      const uint64_t *src = ct_in + (size_t)plane * G::N;
+      auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+      ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
+    }
   } else {
     const int plane = (int)blockIdx.x - n_ct_planes;
     const int i = plane % L;
@@ -278,6 +293,7 @@ struct LaunchArgs {
   WPack wp;       // OP_FWD_PACK, OP_FWD_CT_PACK: layout of the weights (polys: the int32 weights)
   uint64_t *out2; // OP_FWD_CT_PACK: transformed plaintexts (out, in: the ciphertext planes)
   int n_first;    // OP_FWD_CT_PACK: ciphertext planes (the first workgroups)
+  int seeded;     // OP_FWD_CT_PACK: ciphertext component 1 from `seed`
   unsigned grid;
 };
 
@@ -308,10 +324,17 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
                          (const int32_t *)la.polys, c.d_primes, tw_ptr<A>(c, false), (int)c.L);
       break;
     case OP_FWD_CT_PACK:
-      if ((e = prep(k_ntt_fwd_ct_pack<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_ntt_fwd_ct_pack<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in,
-                         la.n_first, la.out2, la.wp, (const int32_t *)la.polys, c.d_primes, tw_ptr<A>(c, false),
-                         (int)c.L);
+      if (la.seeded) {
+        if ((e = prep(k_ntt_fwd_ct_pack<A, LOGN, LOGT, true>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_ntt_fwd_ct_pack<A, LOGN, LOGT, true>), dim3(la.grid), dim3(G::NT), lds, st, la.out,
+                           la.in, la.n_first, la.out2, la.wp, (const int32_t *)la.polys, c.d_primes,
+                           tw_ptr<A>(c, false), (int)c.L, la.seed);
+      } else {
+        if ((e = prep(k_ntt_fwd_ct_pack<A, LOGN, LOGT, false>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_ntt_fwd_ct_pack<A, LOGN, LOGT, false>), dim3(la.grid), dim3(G::NT), lds, st, la.out,
+                           la.in, la.n_first, la.out2, la.wp, (const int32_t *)la.polys, c.d_primes,
+                           tw_ptr<A>(c, false), (int)c.L, la.seed);
+      }
       break;
     case OP_INV:
       if ((e = prep(k_ntt_inv<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
