@@ -259,8 +259,8 @@ he_status he_ppmul(he_ctx *ctx, const he_plan *plan, const uint64_t *a, const ui
   tm.cti = p.d_cti();
   tm.pti = p.d_pti();
   tm.n_out = in.n_ct_out;
-  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*tc, sf, a_hat, a, in.n_ct_in, st); }), "ppmul forward a");
-  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*tc, sf, b_hat, b, in.n_pt, st); }), "ppmul forward b");
+  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd2(*tc, sf, a_hat, a, in.n_ct_in, b_hat, b, in.n_pt, st); }),
+         "ppmul forward a, b");
   HIPCHK(timed(c, st, KK_MAC_INV, [&] { return launch_mac(*tc, sm, out, a_hat, b_hat, tm, false, false, st, 1); }),
          "ppmul multiply + inverse");
   return HE_OK;
@@ -285,8 +285,8 @@ he_status he_cpmul_acc(he_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint
   if (!(flags & HE_IN_NTT)) {
     uint64_t *a = (uint64_t *)w;
     uint64_t *b = (uint64_t *)(w + al256((size_t)K * 2 * c.L * c.N * 8));
-    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, a, ct, K * 2 * c.L, st); }), "cpmul fwd ct");
-    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(c, c.s_fwd, b, pt, K * c.L, st); }), "cpmul fwd pt");
+    HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd2(c, c.s_fwd, a, ct, K * 2 * c.L, b, pt, K * c.L, st); }),
+           "cpmul fwd ct, pt");
     ct_hat = a;
     pt_hat = b;
   }

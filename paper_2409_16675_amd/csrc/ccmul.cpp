@@ -213,7 +213,7 @@ CcLayout layout(const Ctx &c, uint32_t E, uint32_t n_a, uint32_t n_b, uint32_t n
     off += al(bytes);
     return at;
   };
-  l.stage = take((size_t)(n_a > n_b ? n_a : n_b) * 2 * E * plane);
+  l.stage = take((size_t)(n_a + n_b) * 2 * E * plane);   // both lifted operands, transformed in one launch
   l.a_hat = take((size_t)n_a * 2 * E * plane);
   l.b_hat = take((size_t)n_b * 2 * E * plane);
   const size_t xb = (size_t)n_out * 3 * E * plane, db = (size_t)n_out * L * L * plane;
@@ -341,10 +341,12 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
   uint64_t *X = (uint64_t *)(w + l.x), *dig = (uint64_t *)(w + l.dig);
   const Sched sf{ec->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64, c.s_fwd.loge};
   const Sched sm{ec->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64, c.s_mac.loge};
+  uint64_t *stage_b = stage + (size_t)n_a * 2 * E * N;
   HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), ec->f64_ok, stage, a, n_a * 2, N, st); }), "ccmul extend a");
-  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*ec, sf, a_hat, stage, n_a * 2 * E, st); }), "ccmul fwd a");
-  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), ec->f64_ok, stage, b, n_b * 2, N, st); }), "ccmul extend b");
-  HIPCHK(timed(c, st, KK_FWD, [&] { return launch_ntt_fwd(*ec, sf, b_hat, stage, n_b * 2 * E, st); }), "ccmul fwd b");
+  HIPCHK(timed(c, st, KK_RNS, [&] { return launch_rns_extend(cv, (int)L, (int)(E - L), ec->f64_ok, stage_b, b, n_b * 2, N, st); }), "ccmul extend b");
+  HIPCHK(timed(c, st, KK_FWD,
+               [&] { return launch_ntt_fwd2(*ec, sf, a_hat, stage, n_a * 2 * E, b_hat, stage_b, n_b * 2 * E, st); }),
+         "ccmul fwd a, b");
   Terms tt;
   tt.row = d_tl + t_row;
   tt.cti = d_tl + t_ct;

@@ -104,6 +104,9 @@ struct WPack {
 // weights in LDS (layout wp): out [n_polys][L][N]
 hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, const int32_t *w, const WPack &wp,
                                uint32_t n_polys, hipStream_t st);
+// forward transforms of two plane arrays in one launch (in1 -> out1, in2 -> out2)
+hipError_t launch_ntt_fwd2(const Ctx &c, const Sched &s, uint64_t *out1, const uint64_t *in1, uint32_t n1_planes,
+                           uint64_t *out2, const uint64_t *in2, uint32_t n2_planes, hipStream_t st);
 // both in one launch: n_ct_planes ciphertext planes ct_in -> ct_out, and
 // n_polys plaintext polynomials packed from w -> pt_out.  With a seed
 // (2 words), ct_in holds component 0 only ([n][L][N]) and component 1 is

@@ -248,6 +248,18 @@ hipError_t launch_ntt_fwd_pack(const Ctx &c, const Sched &s, uint64_t *out, cons
   return dispatch(c, s, OP_FWD_PACK, la, st);
 }
 
+hipError_t launch_ntt_fwd2(const Ctx &c, const Sched &s, uint64_t *out1, const uint64_t *in1, uint32_t n1_planes,
+                           uint64_t *out2, const uint64_t *in2, uint32_t n2_planes, hipStream_t st) {
+  LaunchArgs la{};
+  la.out = out1;
+  la.in = in1;
+  la.n_first = (int)n1_planes;
+  la.out2 = out2;
+  la.pt = in2;
+  la.grid = n1_planes + n2_planes;
+  return dispatch(c, s, OP_FWD2, la, st);
+}
+
 hipError_t launch_ntt_fwd_ct_pack(const Ctx &c, const Sched &s, uint64_t *ct_out, const uint64_t *ct_in,
                                   uint32_t n_ct_planes, uint64_t *pt_out, const int32_t *w, const WPack &wp,
                                   uint32_t n_polys, hipStream_t st, const uint64_t *seed) {

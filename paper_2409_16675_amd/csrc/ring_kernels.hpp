@@ -43,6 +43,26 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   ntt_forward<A, G>(ar, tw + (size_t)i * G::N, tid, lds, ld, st);
 }
 
+// Forward transforms of two plane arrays in one launch: workgroups below n1
+// take in1 -> out1, the others in2 -> out2 (two small sets run side by side).
+template <class A, int LOGN, int LOGT>
+__global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ntt_fwd2(
+    uint64_t *__restrict__ out1, const uint64_t *__restrict__ in1, int n1, uint64_t *__restrict__ out2,
+    const uint64_t *__restrict__ in2, const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, int L) {
+  using G = Geo<LOGN, LOGT>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
+  const bool first = (int)blockIdx.x < n1;
+  const int plane = first ? (int)blockIdx.x : (int)blockIdx.x - n1;
+  const int i = plane % L;
+  const A ar(primes[i]);
+  const uint64_t *src = (first ? in1 : in2) + (size_t)plane * G::N;
+  uint64_t *dst = (first ? out1 : out2) + (size_t)plane * G::N;
+  auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
+  ntt_forward<A, G>(ar, tw + (size_t)i * G::N, threadIdx.x, lds, ld, st);
+}
+
 // Forward transform of ciphertext planes whose component 1 is regenerated from
 // a seed: plane (j, comp, i) reads component 0 from ct0 [n][L][N] or forms
 // component 1 in registers (no HBM read of c1).
@@ -279,7 +299,7 @@ inline const TwU64 *tw_ptr<ArU64>(const Ctx &c, bool inverse) {
   return (const TwU64 *)(inverse ? c.d_tw_u64_inv : c.d_tw_u64_fwd);
 }
 
-enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED, OP_FWD_PACK, OP_FWD_CT_PACK };
+enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED, OP_FWD_PACK, OP_FWD_CT_PACK, OP_FWD2 };
 
 struct LaunchArgs {
   uint64_t *out;
@@ -291,8 +311,9 @@ struct LaunchArgs {
   int ncomp;
   Seed seed;
   WPack wp;       // OP_FWD_PACK, OP_FWD_CT_PACK: layout of the weights (polys: the int32 weights)
-  uint64_t *out2; // OP_FWD_CT_PACK: transformed plaintexts (out, in: the ciphertext planes)
-  int n_first;    // OP_FWD_CT_PACK: ciphertext planes (the first workgroups)
+  uint64_t *out2; // OP_FWD_CT_PACK: transformed plaintexts (out, in: the ciphertext planes);
+                  // OP_FWD2: second output (out, in: the first array; pt: the second input)
+  int n_first;    // OP_FWD_CT_PACK, OP_FWD2: planes of the first array (the first workgroups)
   int seeded;     // OP_FWD_CT_PACK: ciphertext component 1 from `seed`
   unsigned grid;
 };
@@ -322,6 +343,11 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
       if ((e = prep(k_ntt_fwd_pack<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
       hipLaunchKernelGGL((k_ntt_fwd_pack<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.wp,
                          (const int32_t *)la.polys, c.d_primes, tw_ptr<A>(c, false), (int)c.L);
+      break;
+    case OP_FWD2:
+      if ((e = prep(k_ntt_fwd2<A, LOGN, LOGT>, lds)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_ntt_fwd2<A, LOGN, LOGT>), dim3(la.grid), dim3(G::NT), lds, st, la.out, la.in, la.n_first,
+                         la.out2, la.pt, c.d_primes, tw_ptr<A>(c, false), (int)c.L);
       break;
     case OP_FWD_CT_PACK:
       if (la.seeded) {
