@@ -73,6 +73,23 @@ __device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, uint32_t idx) {
   return __builtin_bit_cast(Tw, v);
 }
 
+// One twiddle entry at an index that every thread of the workgroup shares:
+// the table base is read from the first lane and the table addressed through
+// the constant address space, so the compiler reads the entry with a scalar
+// load into SGPRs (no vector memory instruction and no VGPRs for it).  The
+// tables are written before any kernel that reads them runs.
+#define HE_CONST __attribute__((address_space(4)))
+template <class Tw, class TwP>
+__device__ __forceinline__ Tw load_tw_uniform(TwP tw, uint32_t idx) {
+  const uint64_t a = (uint64_t)(uintptr_t)tw;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+  static_assert(sizeof(Tw) == sizeof(u64x2), "twiddle entries are 16 bytes");
+  const HE_CONST u64x2 *c = (const HE_CONST u64x2 *)(((uint64_t)hi << 32) | lo);
+  return __builtin_bit_cast(Tw, c[idx]);
+}
+
 // Waves per SIMD two (or more) resident workgroups need, given the LDS a plane
 // takes: passed as the second __launch_bounds__ argument so that the compiler
 // keeps the register count low enough for that occupancy.
@@ -264,18 +281,30 @@ struct PassTw {
   typename A::Tw n0, n1;
   template <class TwP>
   __device__ __forceinline__ void load(TwP tw, int tid) {
+    using Tw = typename A::Tw;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      const uint32_t high = (uint32_t)((g << G::LOGT) | tid) >> NLOW;
+      if constexpr (NLOW >= G::LOGT) {
+        // the high index bits hold no thread bits (tid < 2^LOGT <= 2^NLOW):
+        // the same entries for the whole workgroup
+        const uint32_t high = (uint32_t)g >> (NLOW - G::LOGT);
 #pragma unroll
-      for (int u = 0; u < R; ++u)
+        for (int u = 0; u < R; ++u)
 #pragma unroll
-        for (int j = 0; j < (1 << u); ++j)
-          w[g][(1 << u) - 1 + j] = load_tw(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+          for (int j = 0; j < (1 << u); ++j)
+            w[g][(1 << u) - 1 + j] = load_tw_uniform<Tw>(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+      } else {
+        const uint32_t high = (uint32_t)((g << G::LOGT) | tid) >> NLOW;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+#pragma unroll
+          for (int j = 0; j < (1 << u); ++j)
+            w[g][(1 << u) - 1 + j] = load_tw(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+      }
     }
     if constexpr (INV && S0 == 0) {
-      n0 = load_tw(tw, 0);
-      n1 = load_tw(tw, 1);
+      n0 = load_tw_uniform<Tw>(tw, 0);
+      n1 = load_tw_uniform<Tw>(tw, 1);
     }
   }
 };
