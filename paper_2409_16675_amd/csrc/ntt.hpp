@@ -8,7 +8,7 @@
 //
 // Work split: a plane of N = 2^LOGN coefficients is held by NT = 2^LOGT
 // threads, E = N / NT coefficients each in registers.  The LOGN stages are
-// cut into passes of at most LOGE = log2 E stages.  In a pass with first
+// cut into passes of at most LOGE = log2 E stages (PassSplit).  In a pass with first
 // stage S0 and R stages the index bits are [S0 high bits | R pass bits | rest]
 // and each thread owns whole radix-2^R groups (the pass bits live in the
 // register index), so a pass needs no communication; between passes the
@@ -23,23 +23,66 @@ namespace he {
 
 constexpr int kLdsPadShift = 4;
 
+// Stage counts of the passes.  The first pass takes LOGE stages (it reads or
+// writes HBM directly); the rest, with the fewest passes, are sized so that as
+// few twiddle entries as possible go through vector memory.  A pass of R stages
+// needs E - E / 2^R entries per thread, and they are the same across a wave
+// (scalar loads, see PassTw) when its low index bits cover the lane bits:
+// LOGN - S0 - R >= 6 (or >= LOGT when a plane has fewer than 64 threads).  Of
+// the splits with the fewest vector entries the one with the larger passes
+// first is taken.
+struct PassSplit {
+  int n;
+  int r[8];
+};
+constexpr void split_search(int logn, int loge, int logt, int k, int s0, int vec, PassSplit &cur, PassSplit &best,
+                            int &best_vec) {
+  if (k == cur.n) {
+    if (s0 == logn && vec < best_vec) {
+      best_vec = vec;
+      best = cur;
+    }
+    return;
+  }
+  for (int r = loge; r >= 1; --r) {
+    if (s0 + r > logn) continue;
+    const int e = 1 << loge;
+    const bool uniform = logn - s0 - r >= (logt < 6 ? logt : 6);
+    cur.r[k] = r;
+    split_search(logn, loge, logt, k + 1, s0 + r, vec + (uniform ? 0 : e - (e >> r)), cur, best, best_vec);
+  }
+}
+constexpr PassSplit choose_split(int logn, int loge) {
+  PassSplit cur{(logn + loge - 1) / loge, {}}, best = cur;
+  cur.r[0] = loge;
+  int best_vec = 1 << 30;
+  split_search(logn, loge, logn - loge, 1, loge, 0, cur, best, best_vec);
+  return best;
+}
+
 template <int LOGN_, int LOGT_>
 struct Geo {
   static constexpr int LOGN = LOGN_, LOGT = LOGT_;
   static constexpr int N = 1 << LOGN, NT = 1 << LOGT, LOGE = LOGN - LOGT, E = 1 << LOGE;
   static constexpr int NPASS = (LOGN + LOGE - 1) / LOGE;
-  static constexpr int s0(int k) { return k * LOGE; }
-  static constexpr int r(int k) { return (LOGN - k * LOGE) < LOGE ? (LOGN - k * LOGE) : LOGE; }
+  static_assert(NPASS <= 8, "pass table size");
+  static constexpr PassSplit split = choose_split(LOGN, LOGE);
+  static constexpr int r(int k) { return split.r[k]; }
+  static constexpr int s0(int k) {
+    int s = 0;
+    for (int j = 0; j < k; ++j) s += split.r[j];
+    return s;
+  }
+  static_assert(s0(NPASS) == LOGN && split.r[0] == LOGE, "pass split covers the stages");
   static constexpr int LDS_WORDS = N + (N >> kLdsPadShift);
 };
 
 // LDS words of a plane are padded by one word after every 2^kLdsPadShift.
 // LDS serves 16 lanes of a 64-bit access per clock over 32 four-byte banks;
-// with 16 coefficients per thread every pass's pattern (a stride of 1, of 2,
-// or of 32 words at the lane bits that leave the low index bits) then spreads
-// over all 32 banks, where a pad every 32 words left two of the four passes
-// 2-way conflicted (the measured conflict cycles of the transforms match that
-// count exactly).
+// with 16 coefficients per thread every pass's pattern (for N = 2^12 .. 2^14
+// and the pass splits chosen below) then spreads over all 32 banks, where a
+// pad every 32 words left two of the four passes 2-way conflicted (the
+// measured conflict cycles of the transforms match that count exactly).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> kLdsPadShift); }
 __host__ __device__ constexpr int lpad_c(int i) { return i + (i >> kLdsPadShift); }
 // LDS word of linear index j * NT + tid (tid < NT): the two parts have
@@ -73,11 +116,13 @@ __device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, uint32_t idx) {
   return __builtin_bit_cast(Tw, v);
 }
 
-// One twiddle entry at an index that every thread of the workgroup shares:
-// the table base is read from the first lane and the table addressed through
-// the constant address space, so the compiler reads the entry with a scalar
-// load into SGPRs (no vector memory instruction and no VGPRs for it).  The
-// tables are written before any kernel that reads them runs.
+// One twiddle entry at an index that every lane of the wave shares: the table
+// base is read from the first lane and the table addressed through the
+// constant address space, so the compiler reads the entry with a scalar load
+// into SGPRs (no vector memory instruction and no VGPRs for it).  A wave never
+// holds threads of two planes (a plane has at least 64 threads, or is the
+// whole workgroup), so the base is the same in every lane.  The tables are
+// written before any kernel that reads them runs.
 #define HE_CONST __attribute__((address_space(4)))
 template <class Tw, class TwP>
 __device__ __forceinline__ Tw load_tw_uniform(TwP tw, uint32_t idx) {
@@ -286,8 +331,17 @@ struct PassTw {
     for (int g = 0; g < NG; ++g) {
       if constexpr (NLOW >= G::LOGT) {
         // the high index bits hold no thread bits (tid < 2^LOGT <= 2^NLOW):
-        // the same entries for the whole workgroup
+        // the same entries for the whole plane
         const uint32_t high = (uint32_t)g >> (NLOW - G::LOGT);
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+#pragma unroll
+          for (int j = 0; j < (1 << u); ++j)
+            w[g][(1 << u) - 1 + j] = load_tw_uniform<Tw>(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+      } else if constexpr (NLOW >= 6) {
+        // the thread bits left in the high index bits are those above the
+        // lane bits (tid >> 6): the same entries across each wave
+        const uint32_t high = __builtin_amdgcn_readfirstlane((uint32_t)((g << G::LOGT) | tid) >> NLOW);
 #pragma unroll
         for (int u = 0; u < R; ++u)
 #pragma unroll
