@@ -58,8 +58,8 @@ def kernel_src_sha():
 # digest of the sources the counters were taken on.
 TRAFFIC = {
     # (source digest, layer jobs per launch): bytes per launch, with the counter readings
-    ("c8d0f2707b0c9550", 16): {"bytes": 2042459701, "fetch_kib": 136614.8, "fetch_scale": 1.9999,
-                               "write_kib": 1721376.1, "write_scale": 1.0000,
+    ("b656d568a51f8e32", 16): {"bytes": 2037855343, "fetch_kib": 134365.9, "fetch_scale": 1.9999,
+                               "write_kib": 1721376.4, "write_scale": 1.0000,
                                "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x16_hbm_bytes.md"},
 }
 
