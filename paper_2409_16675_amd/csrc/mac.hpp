@@ -56,12 +56,13 @@ struct MacAcc<ArU64> {
   __device__ __forceinline__ uint64_t value() const { return lo; }
 };
 
-// One term for the E coefficients j * NT + tid of a thread: the operand loads
-// of a batch of coefficients are all issued before its first product, so they
-// are in flight together instead of one memory round trip per coefficient.
-// FIRST: the accumulators take the products (no zero start).
-template <class A, int E, int NT, bool FIRST, class P>
-__device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, int tid) {
+// One term for the E coefficients ix(0) .. ix(E-1) of a thread (the slot
+// layout of the consumer): the operand loads of a batch of coefficients are
+// all issued before its first product, so they are in flight together instead
+// of one memory round trip per coefficient.  FIRST: the accumulators take the
+// products (no zero start).
+template <class A, int E, bool FIRST, class P, class Ix>
+__device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, Ix ix) {
   constexpr int B = E < MacAcc<A>::kLoadBatch ? E : MacAcc<A>::kLoadBatch;
 #pragma unroll
   for (int j0 = 0; j0 < E; j0 += B) {
@@ -69,7 +70,7 @@ __device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, 
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       // unsigned 32-bit offsets: a scalar base plus a lane offset, no 64-bit adds
-      const uint32_t k = (uint32_t)((j0 + j) * NT) + (uint32_t)tid;
+      const uint32_t k = ix(j0 + j);
       va[j] = a[k];
       vb[j] = b[k];
     }
@@ -85,13 +86,13 @@ __device__ __forceinline__ void mac_term(const A &ar, MacAcc<A> *acc, P a, P b, 
 // operand planes of term t.  Folds after every kChunk products; a last run of a
 // single product is left unfolded where that is within kOutBoundX100.  An empty
 // term list leaves the accumulators at zero.
-template <class A, int E, int NT, class Ops>
+template <class A, int E, class Ops, class Ix>
 __device__ __forceinline__ void mac_terms(const A &ar, const PrimeK &pk, MacAcc<A> *acc, int t0, int t1, Ops operands,
-                                          int tid) {
+                                          Ix ix) {
   if (t0 >= t1) return;
   {
     auto [a, b] = operands(t0);
-    mac_term<A, E, NT, true>(ar, acc, a, b, tid);
+    mac_term<A, E, true>(ar, acc, a, b, ix);
   }
   int run = 1;   // products since the start or the last fold
   for (int t = t0 + 1; t < t1; ++t) {
@@ -101,7 +102,7 @@ __device__ __forceinline__ void mac_terms(const A &ar, const PrimeK &pk, MacAcc<
       run = 0;
     }
     auto [a, b] = operands(t);
-    mac_term<A, E, NT, false>(ar, acc, a, b, tid);
+    mac_term<A, E, false>(ar, acc, a, b, ix);
     ++run;
   }
   if (run > 1 || !MacAcc<A>::kLoneReduced) {

@@ -13,9 +13,12 @@
 // and each thread owns whole radix-2^R groups (the pass bits live in the
 // register index), so a pass needs no communication; between passes the
 // plane goes through LDS (padded by one word every 16 to spread banks).  The
-// first forward pass reads HBM directly and the last inverse pass writes HBM
-// directly: in both the thread index maps to the low index bits, so those
-// accesses are coalesced.  The bit-reversed side goes through LDS.
+// first and last passes touch HBM (or the producer's registers) directly: the
+// first forward and last inverse pass map the thread index to the low index
+// bits, and the last forward and first inverse pass have no low index bits
+// (each thread holds runs of 2^R consecutive coefficients, adjacent across
+// threads), so all four are coalesced and only the passes in between
+// exchange through LDS.
 #pragma once
 #include "arith.hpp"
 
@@ -402,20 +405,24 @@ __device__ __forceinline__ void fwd_pass(const A &ar, const PassTw<A, G, K, fals
     for (int p = 0; p < (1 << R); ++p) st(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p), v[(g << R) | p]);
 }
 
-// Inverse pass K (stages S0+R-1 down to S0).  B0 is the bound of the transform's input.
-template <class A, class G, int K, int B0X100, class Ld, class St, class Mid>
-__device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true> &twr, int tid, Ld ld, St st,
-                                         Mid mid) {
-  using V = typename A::V;
+// Coefficient index of register slot e = (g << R) | p of thread tid in pass K.
+template <class G, int K>
+__device__ __forceinline__ uint32_t slot_index(int tid, int e) {
+  constexpr int S0 = G::s0(K), R = G::r(K);
+  return (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0) +
+         (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(0, e >> R, e & ((1 << R) - 1));
+}
+
+// Inverse pass K (stages S0+R-1 down to S0) on values already in registers
+// (slot e holds coefficient slot_index<G, K>(tid, e)).  B0 is the bound of the
+// transform's input.
+template <class A, class G, int K, int B0X100, class St, class Mid>
+__device__ __forceinline__ void inv_pass_v(const A &ar, const PassTw<A, G, K, true> &twr, int tid,
+                                           typename A::V (&v)[G::E], St st, Mid mid) {
   constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
   constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
   const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
-  V v[G::E];
-#pragma unroll
-  for (int g = 0; g < NG; ++g)
-#pragma unroll
-    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p));
 #pragma unroll
   for (int uu = 0; uu < R; ++uu) {
     const int u = R - 1 - uu;   // stage S0 + u, processed from the highest down
@@ -447,6 +454,20 @@ __device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true
     for (int p = 0; p < (1 << R); ++p) st(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p), v[(g << R) | p]);
 }
 
+// Inverse pass K reading its input through ld(t, c).
+template <class A, class G, int K, int B0X100, class Ld, class St, class Mid>
+__device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true> &twr, int tid, Ld ld, St st,
+                                         Mid mid) {
+  constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
+  const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
+  typename A::V v[G::E];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p));
+  inv_pass_v<A, G, K, B0X100>(ar, twr, tid, v, st, mid);
+}
+
 // A pass loads and stores the same thread-private set of indices, so passes
 // sharing LDS need only one barrier between them.
 
@@ -462,22 +483,25 @@ struct LdsPut {
   __device__ __forceinline__ void operator()(int t, int c, V v) const { lds[lpad(t) + lpad_c(c)] = v; }
 };
 
-// Forward passes K..NPASS-1, LDS to LDS; `cur` holds pass K's twiddles.  PF:
-// load the next pass's twiddles before this pass's stores (more registers
-// live across the barrier); otherwise after the barrier.
+// Forward passes K..NPASS-2, LDS to LDS; `cur` holds pass K's twiddles and
+// `last` receives pass NPASS-1's (the last pass is run by the caller, to the
+// destination).  PF: load the next pass's twiddles before this pass's stores
+// (more registers live across the barrier); otherwise after the barrier.
 template <class A, class G, int K, bool PF, class TwP>
 __device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds,
-                                               PassTw<A, G, K, false> &cur) {
+                                               PassTw<A, G, K, false> &cur, PassTw<A, G, G::NPASS - 1, false> &last) {
   __syncthreads();
   if constexpr (!PF) cur.load(tw, tid);
-  if constexpr (K + 1 < G::NPASS) {
+  if constexpr (K + 2 < G::NPASS) {
     PassTw<A, G, K + 1, false> nxt;
     fwd_pass<A, G, K>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
       if constexpr (PF) nxt.load(tw, tid);
     });
-    fwd_lds_passes<A, G, K + 1, PF>(ar, tw, tid, lds, nxt);
+    fwd_lds_passes<A, G, K + 1, PF>(ar, tw, tid, lds, nxt, last);
   } else {
-    fwd_pass<A, G, K>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [] {});
+    fwd_pass<A, G, K>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
+      if constexpr (PF) last.load(tw, tid);
+    });
   }
 }
 
@@ -502,21 +526,33 @@ __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typ
 }
 
 // Whole forward transform: ld2(t, c) reads coefficient t + c of the input
-// (coalesced pass-0 order), the result is written through st(i, canonical) in
-// linear order.
+// (coalesced pass-0 order), the result is written through st(i, canonical).
+// The last pass has no low index bits: a thread's 2^R slots of a group are
+// consecutive coefficients and consecutive threads hold adjacent runs, so it
+// writes the destination directly (no final round trip through LDS).  LDS
+// then holds the next-to-last pass's output.
 template <class A, class G, bool PF = true, class TwP, class Ld2, class St>
 __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typename A::V *lds, Ld2 ld2, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
+  using V = typename A::V;
   PassTw<A, G, 0, false> t0;
   t0.load(tw, tid);
-  PassTw<A, G, 1, false> t1;
-  fwd_pass<A, G, 0>(ar, t0, tid, ld2, LdsPut<typename A::V>{lds}, [&] {
-    if constexpr (PF) t1.load(tw, tid);
-  });
-  fwd_lds_passes<A, G, 1, PF>(ar, tw, tid, lds, t1);
+  PassTw<A, G, G::NPASS - 1, false> last;
+  if constexpr (G::NPASS > 2) {
+    PassTw<A, G, 1, false> t1;
+    fwd_pass<A, G, 0>(ar, t0, tid, ld2, LdsPut<V>{lds}, [&] {
+      if constexpr (PF) t1.load(tw, tid);
+    });
+    fwd_lds_passes<A, G, 1, PF>(ar, tw, tid, lds, t1, last);
+  } else {
+    fwd_pass<A, G, 0>(ar, t0, tid, ld2, LdsPut<V>{lds}, [&] {
+      if constexpr (PF) last.load(tw, tid);
+    });
+  }
   __syncthreads();
-#pragma unroll
-  for (int j = 0; j < G::E; ++j) st(j * G::NT + tid, ar.store(lds[lin_lds<G>(tid, j)]));
+  if constexpr (!PF) last.load(tw, tid);
+  auto st_out = [&](int t, int c, V v) { st(t + c, ar.store(v)); };
+  fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
 }
 // The same with ld(i) reading coefficient i.
 template <class A, class G, bool PF = true, class TwP, class Ld, class St>
@@ -524,19 +560,34 @@ __device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typena
   ntt_forward_tc<A, G, PF>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
 }
 
-// Whole inverse transform of values already placed in LDS (linear order, bound
-// B0X100/100 q); pass 0 writes st(i, canonical) in coalesced order.
+// Whole inverse transform of values v already in registers in the layout of
+// its first pass (slot e holds coefficient slot_index<G, NPASS-1>(tid, e), bound
+// B0X100/100 q): that pass has no low index bits, so a producer reading or
+// computing the values pointwise fills it without a round trip through LDS.
+// Pass 0 writes st(i, canonical) in coalesced order.  `first` holds the first
+// pass's twiddles (loaded by the caller, ahead of the values).
 template <class A, class G, int B0X100, bool PF = true, class TwP, class St>
-__device__ __forceinline__ void ntt_inverse_from_lds(const A &ar, TwP tw, int tid, typename A::V *lds, St st) {
+__device__ __forceinline__ void ntt_inverse_regs(const A &ar, TwP tw, int tid, typename A::V *lds,
+                                                 const PassTw<A, G, G::NPASS - 1, true> &first,
+                                                 typename A::V (&v)[G::E], St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
-  PassTw<A, G, G::NPASS - 1, true> first;
-  if constexpr (PF) first.load(tw, tid);
+  using V = typename A::V;
   PassTw<A, G, 0, true> last;
-  inv_lds_passes<A, G, G::NPASS - 1, B0X100, PF>(ar, tw, tid, lds, first, last);
+  if constexpr (G::NPASS > 2) {
+    PassTw<A, G, G::NPASS - 2, true> nxt;
+    inv_pass_v<A, G, G::NPASS - 1, B0X100>(ar, first, tid, v, LdsPut<V>{lds}, [&] {
+      if constexpr (PF) nxt.load(tw, tid);
+    });
+    inv_lds_passes<A, G, G::NPASS - 2, B0X100, PF>(ar, tw, tid, lds, nxt, last);
+  } else {
+    inv_pass_v<A, G, 1, B0X100>(ar, first, tid, v, LdsPut<V>{lds}, [&] {
+      if constexpr (PF) last.load(tw, tid);
+    });
+  }
   __syncthreads();
   if constexpr (!PF) last.load(tw, tid);
-  auto st_out = [&](int t, int c, typename A::V v) { st(t + c, ar.store(v)); };
-  inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<typename A::V>{lds}, st_out, [] {});
+  auto st_out = [&](int t, int c, V x) { st(t + c, ar.store(x)); };
+  inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
 }
 
 }  // namespace he

@@ -97,27 +97,31 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       const HE_GLOBAL uint64_t *b = pt_hat + ((size_t)pti[t] * L + i) * G::N;
       return std::pair<const HE_GLOBAL uint64_t *, const HE_GLOBAL uint64_t *>(a, b);
     };
-    mac_terms<A, G::E, G::NT>(ar, pk, acc, t0, t1, operands, tid_g);
+    mac_terms<A, G::E>(ar, pk, acc, t0, t1, operands, [&](int e) { return slot_index<G, G::NPASS - 1>(tid_g, e); });
+    V v[G::E];
 #pragma unroll
-    for (int j = 0; j < G::E; ++j) lds_g[lin_lds<G>(tid_g, j)] = acc[j].value();
+    for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
+    const auto twi = PTw<A>::inv(jb) + (size_t)i * G::N;
+    PassTw<A, G, G::NPASS - 1, true> first;
+    first.load(twi, tid_g);
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_out) + (size_t)plane * G::N;
     const uint64_t q = pk.q;
     // the accumulate choice is uniform over the task: one inverse transform per
     // store kind keeps the per-coefficient stores free of branches
     if (jb.accumulate) {
-      auto st = [&](int k, uint64_t v) {
+      auto st = [&](int k, uint64_t x) {
         if (valid) {
-          const uint64_t s = dst[(uint32_t)k] + v;
+          const uint64_t s = dst[(uint32_t)k] + x;
           dst[(uint32_t)k] = s >= q ? s - q : s;
         }
       };
-      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100, false>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+      ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100, false>(ar, twi, tid_g, lds_g, first, v, st);
     } else {
       // streaming stores: output planes are not read again by this launch
-      auto st = [&](int k, uint64_t v) {
-        if (valid) __builtin_nontemporal_store(v, &dst[(uint32_t)k]);
+      auto st = [&](int k, uint64_t x) {
+        if (valid) __builtin_nontemporal_store(x, &dst[(uint32_t)k]);
       };
-      ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100, false>(ar, PTw<A>::inv(jb) + (size_t)i * G::N, tid_g, lds_g, st);
+      ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100, false>(ar, twi, tid_g, lds_g, first, v, st);
     }
   }
 }

@@ -203,10 +203,14 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_nt
   const uint64_t *src = in + (size_t)plane * G::N;
   uint64_t *dst = out + (size_t)plane * G::N;
   const int tid = threadIdx.x;
+  const typename A::Tw *twi = tw + (size_t)i * G::N;
+  PassTw<A, G, G::NPASS - 1, true> first;
+  first.load(twi, tid);
+  typename A::V v[G::E];
 #pragma unroll
-  for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = ar.load(src[j * G::NT + tid]);
-  auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = v; };
-  ntt_inverse_from_lds<A, G, 100>(ar, tw + (size_t)i * G::N, tid, lds, st);
+  for (int e = 0; e < G::E; ++e) v[e] = ar.load(src[slot_index<G, G::NPASS - 1>(tid, e)]);
+  auto st = [&](int k, uint64_t x) { dst[(uint32_t)k] = x; };
+  ntt_inverse_regs<A, G, 100>(ar, twi, tid, lds, first, v, st);
 }
 
 // ------------------------------------------------- multiply-accumulate (slots)
@@ -231,7 +235,8 @@ __device__ __forceinline__ int term_ct(const TermArgs &ta, int t) { return ta.ro
 __device__ __forceinline__ int term_pt(const TermArgs &ta, int t) { return ta.row ? ta.pti[t] : t; }
 
 // One workgroup per output plane (o, comp, i): multiply-accumulate the slots in
-// linear order into LDS, then the inverse transform, then store (or add).
+// the layout of the inverse transform's first pass, then the inverse
+// transform, then store (or add).
 // NCOMP: components per operand and output (2 for ciphertexts; 1 for products
 // of plaintext polynomials).
 template <class A, int LOGN, int LOGT, bool ACC, int NCOMP = 2>
@@ -260,19 +265,23 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
     const uint64_t *b = pt_hat + ((size_t)term_pt(ta, t) * L + i) * G::N;
     return std::pair<const uint64_t *, const uint64_t *>(a, b);
   };
-  mac_terms<A, G::E, G::NT>(ar, *pk, acc, t0, t1, operands, tid);
+  mac_terms<A, G::E>(ar, *pk, acc, t0, t1, operands, [&](int e) { return slot_index<G, G::NPASS - 1>(tid, e); });
+  typename A::V v[G::E];
 #pragma unroll
-  for (int j = 0; j < G::E; ++j) lds[lin_lds<G>(tid, j)] = acc[j].value();
+  for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
+  const typename A::Tw *twi = tw + (size_t)i * G::N;
+  PassTw<A, G, G::NPASS - 1, true> first;
+  first.load(twi, tid);
   uint64_t *dst = out + (size_t)plane * G::N;
   const uint64_t q = pk->q;
   if constexpr (ACC) {
-    auto st = [&](int k, uint64_t v) { dst[(uint32_t)k] = canon_add(ar, dst[(uint32_t)k], v, q); };
-    ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, tw + (size_t)i * G::N, tid, lds, st);
+    auto st = [&](int k, uint64_t x) { dst[(uint32_t)k] = canon_add(ar, dst[(uint32_t)k], x, q); };
+    ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100>(ar, twi, tid, lds, first, v, st);
   } else {
     // output planes are not read again here: streaming stores keep them from
     // evicting the operands and twiddles that later planes reuse from L2
-    auto st = [&](int k, uint64_t v) { __builtin_nontemporal_store(v, &dst[(uint32_t)k]); };
-    ntt_inverse_from_lds<A, G, MacAcc<A>::kOutBoundX100>(ar, tw + (size_t)i * G::N, tid, lds, st);
+    auto st = [&](int k, uint64_t x) { __builtin_nontemporal_store(x, &dst[(uint32_t)k]); };
+    ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100>(ar, twi, tid, lds, first, v, st);
   }
 }
 
