@@ -18,7 +18,8 @@
 // bits, and the last forward and first inverse pass have no low index bits
 // (each thread holds runs of 2^R consecutive coefficients, adjacent across
 // threads), so all four are coalesced and only the passes in between
-// exchange through LDS.
+// exchange through LDS (the last forward pass stores directly only for runs
+// of at most 4, see ntt_forward_tc).
 #pragma once
 #include "arith.hpp"
 
@@ -528,9 +529,12 @@ __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typ
 // Whole forward transform: ld2(t, c) reads coefficient t + c of the input
 // (coalesced pass-0 order), the result is written through st(i, canonical).
 // The last pass has no low index bits: a thread's 2^R slots of a group are
-// consecutive coefficients and consecutive threads hold adjacent runs, so it
-// writes the destination directly (no final round trip through LDS).  LDS
-// then holds the next-to-last pass's output.
+// consecutive coefficients and consecutive threads hold adjacent runs.  With
+// R <= 2 it writes the destination directly (no final round trip through
+// LDS; a store instruction then fills at least half of each line it touches).
+// With longer runs a store instruction would touch four times the lines of a
+// linear store, each a quarter filled, which measured slower than the round
+// trip: the pass goes to LDS and the plane is written in linear order.
 template <class A, class G, bool PF = true, class TwP, class Ld2, class St>
 __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typename A::V *lds, Ld2 ld2, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
@@ -551,8 +555,15 @@ __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typ
   }
   __syncthreads();
   if constexpr (!PF) last.load(tw, tid);
-  auto st_out = [&](int t, int c, V v) { st(t + c, ar.store(v)); };
-  fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
+  if constexpr (G::r(G::NPASS - 1) <= 2) {
+    auto st_out = [&](int t, int c, V v) { st(t + c, ar.store(v)); };
+    fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
+  } else {
+    fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, LdsPut<V>{lds}, [] {});
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < G::E; ++j) st(j * G::NT + tid, ar.store(lds[lin_lds<G>(tid, j)]));
+  }
 }
 // The same with ld(i) reading coefficient i.
 template <class A, class G, bool PF = true, class TwP, class Ld, class St>
