@@ -58,8 +58,8 @@ def kernel_src_sha():
 # digest of the sources the counters were taken on.
 TRAFFIC = {
     # (source digest, layer jobs per launch): bytes per launch, with the counter readings
-    ("b656d568a51f8e32", 16): {"bytes": 2037855343, "fetch_kib": 134365.9, "fetch_scale": 1.9999,
-                               "write_kib": 1721376.4, "write_scale": 1.0000,
+    ("bdfa06e730929cd2", 16): {"bytes": 2097973519, "fetch_kib": 138502.4, "fetch_scale": 1.9999,
+                               "write_kib": 1771814.2, "write_scale": 1.0000,
                                "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x16_hbm_bytes.md"},
 }
 
