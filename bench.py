@@ -15,8 +15,12 @@ and weights, all resident in HBM) per launch, exactly --steps layer steps in
 the timed region -- next to the plain per-layer path (separate transform,
 multiply-accumulate and inverse kernels) and the fused per-layer path on the
 same MI355X.  Also reported: transforms per second, the roofline of the
-dominant kernel (timed with HIP events on its launch stream during the timed
-region), serving latency, and the CPU oracle timed on the host cores.
+dominant kernel (timed with HIP events the library records on its launch
+stream around the kernel, on direct launches of the same jobs right after the
+timed region), serving latency, and the CPU oracle timed on the host cores.
+The default of 1024 steps (64 launches, about 60 ms) times the path at the
+clocks it holds under sustained load; the first tens of milliseconds run
+slower.
 """
 import argparse
 import json
@@ -58,8 +62,8 @@ def kernel_src_sha():
 # digest of the sources the counters were taken on.
 TRAFFIC = {
     # (source digest, layer jobs per launch): bytes per launch, with the counter readings
-    ("bdfa06e730929cd2", 16): {"bytes": 2097973519, "fetch_kib": 138502.4, "fetch_scale": 1.9999,
-                               "write_kib": 1771814.2, "write_scale": 1.0000,
+    ("36627d11580bbf3e", 16): {"bytes": 2096340835, "fetch_kib": 137869.3, "fetch_scale": 1.9999,
+                               "write_kib": 1771486.0, "write_scale": 1.0000,
                                "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x16_hbm_bytes.md"},
 }
 
@@ -67,7 +71,7 @@ TRAFFIC = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=1024)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--jobs-per-launch", type=int, default=16,
                     help="layer jobs (steps) the batched path runs per persistent launch")

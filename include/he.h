@@ -280,8 +280,11 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
  * log2 P >= log2 t + log2 N + log2 Q + 18, built with its conversion constants
  * on first use (device memory owned by the context); HE_EUNSUPPORTED if that
  * base would need more than 16 primes in all or more than 8 auxiliary ones.
- * The term lists are copied to the workspace and the call waits for that
- * copy; the rest is asynchronous on stream. */
+ * The term lists are read during the call (the caller may reuse them on
+ * return) and reach the workspace through pinned staging buffers of the
+ * context; the call waits at most for the staging copy of the call two back,
+ * and the rest is asynchronous on stream.  Calls on one context from several
+ * host threads are serialized around the staging. */
 he_status he_ccmul_ws_size(he_ctx *ctx, uint32_t n_a, uint32_t n_b, uint32_t n_out, uint32_t n_terms,
                            uint32_t flags, size_t *bytes);
 he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t *b, uint32_t n_b,

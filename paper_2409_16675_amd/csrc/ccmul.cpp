@@ -332,9 +332,27 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
   for (uint32_t o = 0; o < n_out; ++o)
     for (uint32_t j = 0; j < L; ++j) tl.push_back((int32_t)(o * L + j));
   int32_t *d_tl = (int32_t *)(w + l.terms);
-  // the lists live in host memory of this call: wait until the copy has read them
-  HIPCHK(hipMemcpyAsync(d_tl, tl.data(), tl.size() * 4, hipMemcpyHostToDevice, st), "ccmul term lists");
-  HIPCHK(hipStreamSynchronize(st), "ccmul term lists");
+  {
+    // through one of the context's two pinned staging buffers: wait only for
+    // the copy that last read it (two calls back), so the host prepares this
+    // call while the previous one still runs
+    std::lock_guard<std::mutex> lk(c.cc_mu);
+    const int k = c.cc_next;
+    const size_t bytes = tl.size() * 4;
+    if (c.cc_ev[k]) HIPCHK(hipEventSynchronize(c.cc_ev[k]), "ccmul staging");
+    else HIPCHK(hipEventCreateWithFlags(&c.cc_ev[k], hipEventDisableTiming), "ccmul staging");
+    if (c.cc_pin_bytes[k] < bytes) {
+      if (c.cc_pin[k]) HIPCHK(hipHostFree(c.cc_pin[k]), "ccmul staging");
+      c.cc_pin[k] = nullptr;
+      c.cc_pin_bytes[k] = 0;
+      HIPCHK(hipHostMalloc(&c.cc_pin[k], bytes, hipHostMallocDefault), "ccmul staging");
+      c.cc_pin_bytes[k] = bytes;
+    }
+    std::memcpy(c.cc_pin[k], tl.data(), bytes);
+    HIPCHK(hipMemcpyAsync(d_tl, c.cc_pin[k], bytes, hipMemcpyHostToDevice, st), "ccmul term lists");
+    HIPCHK(hipEventRecord(c.cc_ev[k], st), "ccmul staging");
+    c.cc_next = k ^ 1;
+  }
   if (!n_out) return HE_OK;
 
   uint64_t *stage = (uint64_t *)(w + l.stage), *a_hat = (uint64_t *)(w + l.a_hat), *b_hat = (uint64_t *)(w + l.b_hat);

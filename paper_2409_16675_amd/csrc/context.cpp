@@ -211,6 +211,14 @@ void free_context(Ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipFree(c->d_conv);
   }
+  for (int k = 0; k < 2; ++k) {
+    (void)hipSetDevice(c->device);
+    if (c->cc_ev[k]) {
+      (void)hipEventSynchronize(c->cc_ev[k]);
+      (void)hipEventDestroy(c->cc_ev[k]);
+    }
+    if (c->cc_pin[k]) (void)hipHostFree(c->cc_pin[k]);
+  }
   (void)hipSetDevice(c->device);
   for (void *p : {(void *)c->d_primes, c->d_tw_f64_fwd, c->d_tw_f64_inv, c->d_tw_u64_fwd, c->d_tw_u64_inv})
     if (p) (void)hipFree(p);

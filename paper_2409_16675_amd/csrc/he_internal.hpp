@@ -52,6 +52,14 @@ struct Ctx {
   Ctx *ectx = nullptr;
   void *d_conv = nullptr;
   std::mutex ectx_mu;
+  // pinned staging of the ciphertext product's term lists, two buffers used
+  // in turn; event k completes when the copy that last read buffer k has
+  // (so a call waits for the copy two calls back, not for the previous call)
+  void *cc_pin[2] = {nullptr, nullptr};
+  size_t cc_pin_bytes[2] = {0, 0};
+  hipEvent_t cc_ev[2] = {nullptr, nullptr};
+  int cc_next = 0;
+  std::mutex cc_mu;
 };
 
 he_status build_context(const he_params *p, Ctx **out, uint32_t max_L = 8);
