@@ -96,6 +96,39 @@ def test_accumulated_products_match_oracle_and_decrypt(gpu_lib, N, L, bits):
 
 
 @pytest.mark.gpu
+def test_back_to_back_calls_with_different_term_lists(gpu_lib):
+    # four calls on one context and stream with no synchronization between
+    # them, each with its own term lists, workspace and output: the lists pass
+    # through the context's two staging buffers in turn (the third and fourth
+    # calls reuse the buffers of the first and second), so every output must
+    # still be its own product
+    he = gpu_lib
+    N, L = 1024, 2
+    ctx = he.Context(N, L)
+    g, s, rlk = _keys(ctx, 97)
+    rlk_hat = _rlk_hat(he, ctx, rlk)
+    cts = synth.uniform_residues(g, (4, 2), ctx.q, N)
+    d_cts = he.to_device_u64(cts)
+    lists = [([0, 2, 3], [0, 1, 2], [3, 2, 1]),
+             ([0, 1, 4], [3, 0, 1, 2], [3, 0, 0, 1]),
+             ([0, 3], [2, 2, 1], [0, 1, 3]),
+             ([0, 1, 2, 3, 5], [1, 0, 3, 2, 2], [1, 2, 0, 3, 0])]
+    runs = []
+    print("case ccmul back-to-back N=%d L=%d" % (N, L), flush=True)
+    for row, ai, bi in lists:
+        n_out = len(row) - 1
+        ws = he.workspace(he.he_ccmul_ws_size(ctx.h, 4, 4, n_out, len(ai), 0))
+        out = he.empty_u64((n_out, 2, L, N))
+        he.he_ccmul(ctx.h, d_cts, 4, d_cts, 4, np.array(row, np.int32), np.array(ai, np.int32),
+                    np.array(bi, np.int32), n_out, rlk_hat, out, 0, ws, ws.numel())
+        runs.append((row, ai, bi, out, ws))
+    torch.cuda.synchronize()
+    for k, (row, ai, bi, out, _) in enumerate(runs):
+        want = ccmul.ccmul_acc(cts, cts, row, ai, bi, rlk, ctx.q, ctx.psi, T)
+        assert_equal_u64(he.to_numpy_u64(out), want, "call %d" % k)
+
+
+@pytest.mark.gpu
 def test_conv_mask_products_at_the_benchmark_ring(gpu_lib):
     # [r_x r_w] for the conv-forward workload (batch 16, 3 -> 16 channels,
     # N = 8192, L = 3): 256 outputs of one product each over the plan's term
