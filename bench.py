@@ -35,7 +35,9 @@ METRIC = "CPMul-accumulates/s at N=8192,L=3 (batched vs plain); p50/p99 job late
 PEAK_HBM_GBS = 8000.0
 # fp64 and 32-bit integer VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
-# minimal VALU instruction counts of the exact fp64 arithmetic
+# minimal VALU instruction counts of the exact fp64 arithmetic: 6 per modular
+# product, 2 more per butterfly (sum and difference), 8 per multiply-accumulate
+# term (product with its quotient companion formed, plus the add)
 OPS_MODMUL = 6          # mul, fma, mul, rndne, fma, add
 OPS_BFLY = OPS_MODMUL + 2
 OPS_MAC_TERM = OPS_MODMUL + 2   # quotient companion mul + accumulate add
