@@ -216,15 +216,16 @@ constexpr PassPlan plan_gs(int R, double b_in) {
 // the Gentleman-Sande sum x + y doubles the bound of the slots whose lower pass
 // bits are zero while the product side stays below mul_out, so only the
 // growing slots are reduced (before a stage whose sum would leave the limit,
-// and at the end of the pass when above kEndRed).
+// and at the end of the pass when above end_red).  In the last pass (LAST,
+// stages down to 0) stage 0 multiplies both outputs (N^-1 folded in), and no
+// slot is reduced at the end: the canonical store reduces every value.
 struct GsPlan {
   uint32_t red[6];   // red[uu]: slots reduced before stage uu; red[R]: slots reduced at the end
   double b_out;
 };
-constexpr double kEndRed = 2.0;
 
 template <class A>
-constexpr GsPlan plan_gs_slots(int R, double b_in) {
+constexpr GsPlan plan_gs_slots(int R, double b_in, bool last, double end_red) {
   GsPlan pl{{0u, 0u, 0u, 0u, 0u, 0u}, b_in};
   double b[32] = {};
   const int n = 1 << R;
@@ -239,7 +240,7 @@ constexpr GsPlan plan_gs_slots(int R, double b_in) {
         m |= (1u << p) | (1u << p2);
         s = 2.0 * A::kReduced;
       }
-      b[p] = s;
+      b[p] = (last && uu == R - 1) ? A::mul_out(s) : s;
       b[p2] = A::mul_out(s);
     }
     pl.red[uu] = m;
@@ -247,7 +248,7 @@ constexpr GsPlan plan_gs_slots(int R, double b_in) {
   uint32_t e = 0;
   double mx = 0.0;
   for (int p = 0; p < n; ++p) {
-    if (b[p] > kEndRed && A::kLimit < 100.0) {
+    if (!last && b[p] > end_red && A::kLimit < 100.0) {
       e |= 1u << p;
       b[p] = A::kReduced;
     }
@@ -267,10 +268,41 @@ constexpr double fwd_bound_in(int k) {
 }
 // Inverse passes run k = NPASS-1 down to 0; the input is canonical (or a reduced accumulator).
 template <class A, class G>
-constexpr double inv_bound_in(int k, double b0) {
+constexpr double inv_bound_in(int k, double b0, double end_red) {
   double b = b0;
-  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs_slots<A>(G::r(j), b).b_out;
+  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs_slots<A>(G::r(j), b, j == 0, end_red).b_out;
   return b;
+}
+// Reductions per thread over a whole inverse transform, and the end-of-pass
+// threshold (in units of q) that needs the fewest for this geometry and input
+// bound: a low threshold reduces more at pass ends, a high one more inside
+// the next pass.
+template <class A, class G>
+constexpr int inv_reductions(double b0, double end_red) {
+  int tot = 0;
+  double b = b0;
+  for (int j = G::NPASS - 1; j >= 0; --j) {
+    const GsPlan p = plan_gs_slots<A>(G::r(j), b, j == 0, end_red);
+    int c = 0;
+    for (int u = 0; u <= G::r(j); ++u) c += __builtin_popcount(p.red[u]);
+    tot += c * (G::E >> G::r(j));
+    b = p.b_out;
+  }
+  return tot;
+}
+template <class A, class G>
+constexpr double inv_end_red(double b0) {
+  constexpr double cands[] = {2.0, 2.5, 3.0, 3.5, 4.0};
+  double best = cands[0];
+  int best_n = inv_reductions<A, G>(b0, cands[0]);
+  for (double c : cands) {
+    const int n = inv_reductions<A, G>(b0, c);
+    if (n < best_n) {
+      best_n = n;
+      best = c;
+    }
+  }
+  return best;
 }
 
 // ------------------------------------------------------------------- butterflies
@@ -421,7 +453,8 @@ template <class A, class G, int K, int B0X100, class St, class Mid>
 __device__ __forceinline__ void inv_pass_v(const A &ar, const PassTw<A, G, K, true> &twr, int tid,
                                            typename A::V (&v)[G::E], St st, Mid mid) {
   constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
-  constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0));
+  constexpr double end_red = inv_end_red<A, G>(B0X100 / 100.0);
+  constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0, end_red), K == 0, end_red);
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
   const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
 #pragma unroll
