@@ -192,9 +192,14 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
     he.he_batch_run(prof, stream)
     he.he_batch_sync(prof, stream)
     k0 = he.he_batch_get_info(prof)
-    for _ in range(max(1, full)):
-        he.he_batch_run(prof, stream)
-    he.he_batch_sync(prof, stream)
+    n_prof = max(1, full)
+    while n_prof > 0:
+        # the library keeps the events of at most 64 profiled runs between syncs
+        c = min(64, n_prof)
+        for _ in range(c):
+            he.he_batch_run(prof, stream)
+        he.he_batch_sync(prof, stream)
+        n_prof -= c
     k1 = he.he_batch_get_info(prof)
     he.he_batch_destroy(prof)
     kern_ms = (k1["kernel_ms"] - k0["kernel_ms"]) / (k1["kernel_launches"] - k0["kernel_launches"])
