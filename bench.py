@@ -209,7 +209,7 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
 
 def time_seeded(he, torch, wl, steps, warmup):
     """The fused per-layer path with input component 1 regenerated from a seed
-    (only c0 resident; Section 6).  Returns seconds per step and whether the
+    (only c0 resident; Section 7, Discussion).  Returns seconds per step and whether the
     output equals the same layer on the expanded ciphertexts."""
     ctx, plan, info = wl["ctx"], wl["plan"], wl["info"]
     seed = (0x5EED, 0xC1)

@@ -226,7 +226,7 @@ he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes);
 he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in, const void *plain,
                          uint64_t *ct_out, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
-/* Seeded component c1 (Section 6: the client sends a seed instead of the
+/* Seeded component c1 (Section 7, Discussion: the client sends a seed instead of the
  * uniform c1; about half the upload).  Coefficient k of component 1 of
  * ciphertext j at prime i is (w0 2^64 + w1) mod q_i, where (w0, w1, w2, w3) is
  * the Philox4x64-10 block (Salmon et al., SC 2011) of counter (k, j, i, 0)

@@ -352,7 +352,7 @@ void orc_negacyclic_mul_planes(const uint64_t *a, const uint64_t *b, uint32_t n,
 
 /* ---------------------------------------------------------------- seeded c1
  * The client may send a seed instead of the uniform ciphertext component c1,
- * the server regenerating c1 from it (Section 6, discussion of upload cost).
+ * the server regenerating c1 from it (Section 7, Discussion, on the upload cost).
  * Generator: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC 2011), a counter-based bijection of a
  * 256-bit counter under a 128-bit key: ten rounds, each multiplying two

@@ -139,16 +139,23 @@ def dw_terms(B, M, cb):
     return np.array(row, np.int32), np.array(cti, np.int32), np.array(pti, np.int32)
 
 
-def dw_extract(poly, g, M_c_range):
-    """dW[c, a, b] for the channels of one block from block-local offsets."""
-    c0, c1 = M_c_range
+def dw_extract(polys, g):
+    """Weight gradient from the products of a weight-gradient layer: polys[M, cb, N]
+    (output (m, k) of dw_terms) -> dW[M, C, hk, hk] with hk = H + 2P - h' + 1, where
+    h' = g.h is the side of the dY "kernel".  Channel c of block k = c // Cw sits at
+    offset (c % Cw) * S, and dW[m, c, a, b] is the correlation coefficient at
+    (a - P + h' - 1, b - P + h' - 1) of that channel (Section 2: dW is the
+    correlation of the padded input with dY)."""
+    M = polys.shape[0]
     hp = g.h
-    out = np.zeros((c1 - c0, g.H + 2 * g.P - hp + 1, g.W + 2 * g.P - hp + 1), dtype=np.int64)
-    for c in range(c0, c1):
-        cc = c - c0
-        for a in range(out.shape[1]):
-            for b in range(out.shape[2]):
-                out[cc, a, b] = poly[cc * g.S + (a - g.P + hp - 1) * g.O + (b - g.P + hp - 1)]
+    hk = g.H + 2 * g.P - hp + 1
+    out = np.zeros((M, g.C, hk, hk), dtype=np.int64)
+    for m in range(M):
+        for c in range(g.C):
+            k, cc = divmod(c, g.Cw)
+            for a in range(hk):
+                for b in range(hk):
+                    out[m, c, a, b] = polys[m, k, cc * g.S + (a - g.P + hp - 1) * g.O + (b - g.P + hp - 1)]
     return out
 
 

@@ -1,4 +1,4 @@
-// Regeneration of the uniform ciphertext component c1 from a seed (Section 6:
+// Regeneration of the uniform ciphertext component c1 from a seed (Section 7, Discussion:
 // the client sends a seed instead of c1 and the server expands it).
 //
 // Coefficient k of component 1 of ciphertext j at prime i is

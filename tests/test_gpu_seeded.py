@@ -1,4 +1,4 @@
-"""GPU parity of the seeded ciphertext component c1 (Section 6: the client sends
+"""GPU parity of the seeded ciphertext component c1 (Section 7, Discussion: the client sends
 a seed instead of c1, the server regenerates it): the expansion against the
 oracle, and the conv layer with regenerated c1 against the same layer on the
 full ciphertexts, against the oracle, and through decryption."""

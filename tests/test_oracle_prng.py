@@ -1,4 +1,4 @@
-"""Oracle pins for the seeded ciphertext component c1 (Section 6: the client
+"""Oracle pins for the seeded ciphertext component c1 (Section 7, Discussion: the client
 sends a seed instead of c1 and the server regenerates it).
 
 The generator is Philox4x64-10; numpy ships an implementation of the same
