@@ -245,6 +245,7 @@ def time_ppmul(he, torch, wl, steps, warmup):
     a = he.to_device_u64(g.integers(0, t, size=(info["n_ct_in"], N), dtype=np.uint64))
     b = he.to_device_u64(g.integers(0, t, size=(info["n_pt"], N), dtype=np.uint64))
     out = he.empty_u64((info["n_ct_out"], N))
+    he.he_ctx_prepare(ctx.h, he.HE_PREPARE_PPMUL)
     ws = he.workspace(he.he_ppmul_ws_size(plan.h, 0))
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -274,6 +275,7 @@ def time_ccmul(he, torch, wl, steps, warmup):
     rlk = he.to_device_u64(synth.uniform_residues(g, (L, 2), ctx.q, N))
     n_out = info["n_ct_out"]
     out = he.empty_u64((n_out, 2, L, N))
+    he.he_ctx_prepare(ctx.h, he.HE_PREPARE_CCMUL, n_out, len(cti))
     ws = he.workspace(he.he_ccmul_ws_size(ctx.h, info["n_ct_in"], info["n_pt"], n_out, len(cti), 0))
     stream = torch.cuda.current_stream()
 

@@ -88,6 +88,21 @@ he_status he_ctx_moduli(const he_ctx *ctx, uint64_t *q_out, uint64_t *psi_out);
 /* Ring degree, prime count, plaintext modulus and arithmetic in use (any may be NULL). */
 he_status he_ctx_info(const he_ctx *ctx, uint32_t *N, uint32_t *L, uint64_t *t, uint32_t *arith);
 
+/* Device resources of the protocol steps beside the layer path, built ahead
+ * of time so that the hot calls allocate nothing:
+ *   HE_PREPARE_PPMUL  the ring of the plaintext modulus, Z_t[X]/(X^N+1), for
+ *                     he_ppmul (HE_EUNSUPPORTED unless t is prime and 1 mod 2N);
+ *   HE_PREPARE_CCMUL  the extended base Q u P of he_ccmul with its conversion
+ *                     constants, and two pinned staging buffers for term lists
+ *                     of up to ccmul_max_out outputs and ccmul_max_terms
+ *                     products (a later call with larger values grows them).
+ * Allocates device and pinned host memory owned by the context; not to be
+ * called while calls on the same context run.  he_ppmul, he_ccmul and
+ * he_ccmul_ws_size return HE_EINVAL until their resources are prepared. */
+#define HE_PREPARE_PPMUL 0x1u
+#define HE_PREPARE_CCMUL 0x2u
+he_status he_ctx_prepare(he_ctx *ctx, uint32_t ops, uint32_t ccmul_max_out, uint32_t ccmul_max_terms);
+
 /* Kernel schedule used for one operation: arithmetic (HE_ARITH_F64 / HE_ARITH_U64)
  * and log2 of the coefficients each thread holds (3, 4 or 5; the plane is split
  * over N >> loge threads, which must be 64..1024).  Every schedule returns the
@@ -278,13 +293,15 @@ he_status he_extract_output(const he_plan *plan, const int64_t *polys, int64_t *
  * ws: device, he_ccmul_ws_size() bytes for the same sizes and flags.
  * The exact rounding runs on an extended base Q u P of auxiliary primes with
  * log2 P >= log2 t + log2 N + log2 Q + 18, built with its conversion constants
- * on first use (device memory owned by the context); HE_EUNSUPPORTED if that
- * base would need more than 16 primes in all or more than 8 auxiliary ones.
- * The term lists are read during the call (the caller may reuse them on
- * return) and reach the workspace through pinned staging buffers of the
- * context; the call waits at most for the staging copy of the call two back,
- * and the rest is asynchronous on stream.  Calls on one context from several
- * host threads are serialized around the staging. */
+ * by he_ctx_prepare(HE_PREPARE_CCMUL) (device memory owned by the context;
+ * HE_EUNSUPPORTED there if that base would need more than 16 primes in all or
+ * more than 8 auxiliary ones; HE_EINVAL here before it).  The term lists are
+ * read during the call (the caller may reuse them on return) and reach the
+ * workspace through the context's two pinned staging buffers (HE_EINVAL if
+ * they are larger than he_ctx_prepare sized them for); the call waits at most
+ * for the staging copy of the call two back, and the rest is asynchronous on
+ * stream.  Allocates nothing.  Calls on one context from several host threads
+ * are serialized around the staging. */
 he_status he_ccmul_ws_size(he_ctx *ctx, uint32_t n_a, uint32_t n_b, uint32_t n_out, uint32_t n_terms,
                            uint32_t flags, size_t *bytes);
 he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t *b, uint32_t n_b,
@@ -303,16 +320,24 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
  *      pi_x of the masked input block);
  * b    device [n_pt][N] residues in [0, t) (the weight-side polynomials);
  * out  device [n_ct_out][N], written, residues in [0, t).
- * Needs t prime with t = 1 mod 2N (65537 serves every N <= 2^15), else
- * HE_EUNSUPPORTED; the transforms of that ring are built on first use (device
- * memory owned by the context).  flags: HE_VALIDATE (HE_ERANGE if an input is
- * not below t).  ws: device, he_ppmul_ws_size() bytes.  Asynchronous on
- * `stream` unless validating. */
+ * The transforms of that ring are built by he_ctx_prepare(HE_PREPARE_PPMUL),
+ * which needs t prime with t = 1 mod 2N (65537 serves every N <= 2^15);
+ * HE_EINVAL before it.  flags: HE_VALIDATE (HE_ERANGE if an input is not
+ * below t).  ws: device, he_ppmul_ws_size() bytes.  Allocates nothing;
+ * asynchronous on `stream` unless validating. */
 he_status he_ppmul_ws_size(const he_plan *plan, uint32_t flags, size_t *bytes);
 he_status he_ppmul(he_ctx *ctx, const he_plan *plan, const uint64_t *a, const uint64_t *b, uint64_t *out,
                    uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ----------------------------------------------- test-only encryption (client) */
+
+/* Secret key of the test-only client (Section 2 "HE": the client holds the
+ * key; ternary secret as in BFV): sk[k] = floor(3 w / 2^64) - 1 in {-1, 0, 1},
+ * with w the first 64-bit word of the Philox4x64-10 block (Salmon et al.,
+ * SC 2011) of counter (k, 0, 0, 2^64 - 1) under key (seed, 0) -- the last
+ * counter word keeps these blocks apart from those of the seeded component 1.
+ * sk host int8 [N].  Host only: no device work, no allocation. */
+he_status he_keygen(const he_ctx *ctx, uint64_t seed, int8_t *sk);
 
 /* BFV-style secret-key encryption (a reading of Section 2 "HE", which encrypts
  * with a public key; secret-key encryption decrypts identically):
@@ -375,8 +400,17 @@ he_status he_batch_rebind(he_batch *b, uint32_t index, const he_job *job);
 /* Launch the whole batch on `stream` (asynchronous).  HE_EINVAL with
  * HE_BATCH_PROFILE after 64 runs without a sync. */
 he_status he_batch_run(he_batch *b, void *stream);
-/* Wait for `stream` and report HE_ETIMEOUT if a dependency wait hit its bound. */
+/* Wait for `stream` and report HE_ETIMEOUT if a dependency wait of any run
+ * since the previous sync hit its bound (the flag stays set over later runs and
+ * is cleared once reported; the outputs of such runs are not to be trusted). */
 he_status he_batch_sync(he_batch *b, void *stream);
+/* Bound on the polls of one dependency wait inside the persistent kernel
+ * (default about 2^20, about a second at the longest back-off); a wait that
+ * reaches it gives up, the run carries on and he_batch_sync reports
+ * HE_ETIMEOUT.  Applies to direct launches and to graphs captured by a later
+ * he_batch_build.  A watchdog knob, and the host-side way to test that path:
+ * every workgroup still finishes its tasks. */
+he_status he_batch_set_spin_limit(he_batch *b, uint32_t polls);
 he_status he_batch_get_info(const he_batch *b, he_batch_info *info);
 he_status he_batch_destroy(he_batch *b);
 

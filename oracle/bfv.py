@@ -104,3 +104,20 @@ def noise_bits(ct, s, m, q, psi, t):
             r -= Q
         worst = max(worst, abs(r))
     return worst.bit_length()
+
+
+def ternary_from_word(w):
+    """A 64-bit word to {-1, 0, 1}: floor(3 w / 2^64) - 1 (the three thirds of
+    [0, 2^64), each within one word of 2^64 / 3)."""
+    return (3 * int(w) >> 64) - 1
+
+
+def keygen(seed, N):
+    """Ternary secret key from a 64-bit seed: sk[k] = ternary_from_word(w), w the
+    first word of the Philox4x64-10 block of counter (k, 0, 0, 2^64 - 1) under
+    key (seed, 0).  The generator is the published one (pinned to numpy's); the
+    map to {-1, 0, 1} is the key generator's stated definition."""
+    out = np.empty(N, dtype=np.int8)
+    for k in range(N):
+        out[k] = ternary_from_word(core.philox4x64([k, 0, 0, (1 << 64) - 1], [seed, 0])[0])
+    return out

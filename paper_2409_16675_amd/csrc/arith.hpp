@@ -57,6 +57,10 @@ struct ArF64 {
   static constexpr double kCanon = 1.0;                 // canonical load
   static constexpr double kReduced = 0.51;              // after reduce()
   static constexpr double mul_out(double b_in) { return 0.5 + 0.25 * b_in + 0.01; }
+  // mulv forms the quotient companion in the kernel, fl(b * fl(1/q)), so the
+  // quotient estimate carries three roundings of |y b / q| <= b_in q < b_in 2^50:
+  // at most 3 * 2^-53 * b_in * 2^50 = 0.375 b_in, plus 1/2 from rint
+  static constexpr double mulv_out(double b_in) { return 0.5 + 0.375 * b_in + 0.01; }
 
   __device__ __forceinline__ explicit ArF64(const PrimeK &p) : q(p.qd), qinv(p.qinv) {}
 

@@ -240,6 +240,7 @@ he_status he_batch_build(he_batch *b, uint32_t flags) {
   if ((e = hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(PTask))) != hipSuccess ||
       (e = hipMalloc(&b->d_jobs, std::max<size_t>(1, nj) * sizeof(PJob))) != hipSuccess ||
       (e = hipMalloc(&b->d_ctl, b->ctl_words * 4)) != hipSuccess ||
+      (e = hipMemset(b->d_ctl, 0, b->ctl_words * 4)) != hipSuccess ||
       (tasks.size() && (e = hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(PTask), hipMemcpyHostToDevice)) != hipSuccess) ||
       (nj && (e = hipMemcpy(b->d_jobs, pjobs.data(), nj * sizeof(PJob), hipMemcpyHostToDevice)) != hipSuccess)) {
     release(b);
@@ -337,10 +338,21 @@ he_status he_batch_sync(he_batch *b, void *stream) {
     b->info.kernel_launches++;
     b->ev_next = (k + 1) % he_batch::kProfRing;
   }
+  // the flag is sticky over the runs since the last sync (the launches leave it
+  // alone): read it, and clear it once reported
   uint32_t err = 0;
   e = hipMemcpy(&err, b->d_ctl + CTL_ERR, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "batch status");
-  if (err) return fail(HE_ETIMEOUT, "a dependency wait in the persistent kernel hit its bound");
+  if (err) {
+    if ((e = hipMemset(b->d_ctl + CTL_ERR, 0, 4)) != hipSuccess) return hip_fail(e, "batch status reset");
+    return fail(HE_ETIMEOUT, "a dependency wait in the persistent kernel hit its bound");
+  }
+  return HE_OK;
+}
+
+he_status he_batch_set_spin_limit(he_batch *b, uint32_t polls) {
+  if (!b) return fail(HE_EINVAL, "null batch");
+  b->spin_limit = polls;
   return HE_OK;
 }
 

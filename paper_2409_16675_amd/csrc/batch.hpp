@@ -64,8 +64,11 @@ struct XQ {
   uint32_t b[kXcds + 1];   // queue bounds in the task table
 };
 // ev0 / ev1 (optional): recorded on `st` right before and after the persistent kernel.
+// clear_err: zero the error flag with the other control words (otherwise it
+// stays set from earlier launches until the caller clears it).
 hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
-                             uint32_t strict, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                             uint32_t strict, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                             bool clear_err = false);
 
 }  // namespace he

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "he_internal.hpp"
+#include "plan.hpp"
 
 namespace he {
 
@@ -118,3 +119,36 @@ he_status client_decrypt_crt(const Ctx &c, const uint64_t *x, uint32_t n_ct, int
 }
 
 }  // namespace he
+
+namespace {
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC 2011) on the host: ten
+// rounds of two 64x64 -> 128-bit products of counter words with fixed odd
+// multipliers, the halves mixed with the other two words and the key, the key
+// stepping by two Weyl constants per round.
+void philox4x64_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    const unsigned __int128 p0 = (unsigned __int128)M0 * c[0], p1 = (unsigned __int128)M1 * c[2];
+    const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0, hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    c[0] = hi1 ^ c[1] ^ k0;
+    c[1] = lo1;
+    c[2] = hi0 ^ c[3] ^ k1;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+}  // namespace
+
+extern "C" he_status he_keygen(const he_ctx *ctx, uint64_t seed, int8_t *sk) {
+  if (!ctx || !sk) return he::fail(HE_EINVAL, "null argument");
+  const uint32_t N = ctx->c->N;
+  for (uint32_t k = 0; k < N; ++k) {
+    uint64_t c[4] = {k, 0, 0, ~0ull};
+    philox4x64_host(c, seed, 0);
+    // floor(3 w / 2^64) in {0, 1, 2}: within 2^-63 of uniform
+    sk[k] = (int8_t)((int)(((unsigned __int128)c[0] * 3u) >> 64) - 1);
+  }
+  return HE_OK;
+}

@@ -6,6 +6,7 @@
 
 namespace he {
 he_status client_decrypt_crt(const Ctx &c, const uint64_t *x, uint32_t n_ct, int64_t *m);
+he_status ccmul_prepare(Ctx &c, uint32_t max_out, uint32_t max_terms);
 
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
@@ -198,8 +199,15 @@ extern "C" {
 
 // ---------------------------------------------------------------- plaintext product
 // The ring of the plaintext modulus: one prime q = t (an NTT-friendly t such
-// as 65537 = 2^16 + 1 is 1 mod 2N for every N <= 2^15), built on first use.
+// as 65537 = 2^16 + 1 is 1 mod 2N for every N <= 2^15), built by he_ctx_prepare.
 static he_status t_ring(Ctx &c, Ctx **out) {
+  std::lock_guard<std::mutex> g(c.tctx_mu);
+  if (!c.tctx) return fail(HE_EINVAL, "plaintext product not prepared: call he_ctx_prepare with HE_PREPARE_PPMUL");
+  *out = c.tctx;
+  return HE_OK;
+}
+
+static he_status t_ring_build(Ctx &c) {
   std::lock_guard<std::mutex> g(c.tctx_mu);
   if (!c.tctx) {
     const uint64_t q = c.t;
@@ -215,7 +223,20 @@ static he_status t_ring(Ctx &c, Ctx **out) {
       return fail(HE_EUNSUPPORTED, "the plaintext product needs t prime with t = 1 mod 2N");
     c.tctx = tc;
   }
-  *out = c.tctx;
+  return HE_OK;
+}
+
+he_status he_ctx_prepare(he_ctx *ctx, uint32_t ops, uint32_t ccmul_max_out, uint32_t ccmul_max_terms) {
+  if (!ctx) return fail(HE_EINVAL, "null context");
+  if (ops & ~(uint32_t)(HE_PREPARE_PPMUL | HE_PREPARE_CCMUL)) return fail(HE_EINVAL, "unknown HE_PREPARE_* bits");
+  Ctx &c = *ctx->c;
+  hipError_t e = hipSetDevice(c.device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (ops & HE_PREPARE_PPMUL) {
+    he_status s = t_ring_build(c);
+    if (s != HE_OK) return s;
+  }
+  if (ops & HE_PREPARE_CCMUL) return ccmul_prepare(c, ccmul_max_out, ccmul_max_terms);
   return HE_OK;
 }
 

@@ -136,7 +136,8 @@ void fill_conv(RnsConv &cv, const std::vector<uint64_t> &q, const std::vector<ui
   }
 }
 
-he_status ext_ring(Ctx &c, Ctx **ec, const RnsConv **conv) {
+// Build the extended base (once; later calls return it).
+he_status ext_ring_build(Ctx &c, Ctx **ec, const RnsConv **conv) {
   std::lock_guard<std::mutex> g(c.ectx_mu);
   if (!c.ectx) {
     if (c.L > (uint32_t)kRnsMax) return fail(HE_EUNSUPPORTED, "the ciphertext product supports at most 8 primes");
@@ -197,6 +198,21 @@ he_status ext_ring(Ctx &c, Ctx **ec, const RnsConv **conv) {
   return HE_OK;
 }
 
+// The extended base if he_ctx_prepare built it, else HE_EINVAL (hot calls never build it).
+he_status ext_ring(Ctx &c, Ctx **ec, const RnsConv **conv) {
+  std::lock_guard<std::mutex> g(c.ectx_mu);
+  if (!c.ectx) return fail(HE_EINVAL, "ciphertext product not prepared: call he_ctx_prepare with HE_PREPARE_CCMUL");
+  *ec = c.ectx;
+  *conv = (const RnsConv *)c.d_conv;
+  return HE_OK;
+}
+
+// int32 words of the device term lists of one call: tensor rows and pairs,
+// then the relinearization rows and pairs
+size_t cc_list_words(uint32_t n_out, uint32_t n_terms, uint32_t L) {
+  return 3 * (size_t)n_out + 1 + 8 * (size_t)n_terms + (size_t)n_out + 1 + 2 * (size_t)n_out * L;
+}
+
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct CcLayout {
@@ -219,12 +235,38 @@ CcLayout layout(const Ctx &c, uint32_t E, uint32_t n_a, uint32_t n_b, uint32_t n
   const size_t xb = (size_t)n_out * 3 * E * plane, db = (size_t)n_out * L * L * plane;
   l.x = take(xb > db ? xb : db);                       // tensor slots, then the transformed digits
   l.dig = take((size_t)n_out * L * plane);             // d2: digit j is its residue mod q_j
-  l.terms = take(4 * ((3 * (size_t)n_out + 1) + 8 * (size_t)n_terms + ((size_t)n_out + 1) + 2 * (size_t)n_out * L));
+  l.terms = take(4 * cc_list_words(n_out, n_terms, (uint32_t)L));
   l.flag = take((flags & HE_VALIDATE) ? 256 : 0);
   l.total = off;
   return l;
 }
 }  // namespace
+
+// The extended base, its constants, and the two pinned staging buffers of the
+// term lists sized for calls of up to max_out outputs and max_terms products.
+he_status ccmul_prepare(Ctx &c, uint32_t max_out, uint32_t max_terms) {
+  Ctx *ec = nullptr;
+  const RnsConv *cv = nullptr;
+  he_status s = ext_ring_build(c, &ec, &cv);
+  if (s != HE_OK) return s;
+  std::lock_guard<std::mutex> lk(c.cc_mu);
+  const size_t bytes = 4 * cc_list_words(max_out, max_terms, c.L);
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipSuccess;
+    if (!c.cc_ev[k]) e = hipEventCreateWithFlags(&c.cc_ev[k], hipEventDisableTiming);
+    else e = hipEventSynchronize(c.cc_ev[k]);
+    if (e != hipSuccess) return hip_fail(e, "ccmul staging event");
+    if (c.cc_pin_bytes[k] < bytes) {
+      if (c.cc_pin[k] && (e = hipHostFree(c.cc_pin[k])) != hipSuccess) return hip_fail(e, "ccmul staging");
+      c.cc_pin[k] = nullptr;
+      c.cc_pin_bytes[k] = 0;
+      if ((e = hipHostMalloc(&c.cc_pin[k], bytes, hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "ccmul staging");
+      c.cc_pin_bytes[k] = bytes;
+    }
+  }
+  return HE_OK;
+}
 }  // namespace he
 
 using namespace he;
@@ -339,15 +381,9 @@ he_status he_ccmul(he_ctx *ctx, const uint64_t *a, uint32_t n_a, const uint64_t 
     std::lock_guard<std::mutex> lk(c.cc_mu);
     const int k = c.cc_next;
     const size_t bytes = tl.size() * 4;
-    if (c.cc_ev[k]) HIPCHK(hipEventSynchronize(c.cc_ev[k]), "ccmul staging");
-    else HIPCHK(hipEventCreateWithFlags(&c.cc_ev[k], hipEventDisableTiming), "ccmul staging");
-    if (c.cc_pin_bytes[k] < bytes) {
-      if (c.cc_pin[k]) HIPCHK(hipHostFree(c.cc_pin[k]), "ccmul staging");
-      c.cc_pin[k] = nullptr;
-      c.cc_pin_bytes[k] = 0;
-      HIPCHK(hipHostMalloc(&c.cc_pin[k], bytes, hipHostMallocDefault), "ccmul staging");
-      c.cc_pin_bytes[k] = bytes;
-    }
+    if (!c.cc_ev[k] || c.cc_pin_bytes[k] < bytes)
+      return fail(HE_EINVAL, "term lists larger than he_ctx_prepare sized the staging for");
+    HIPCHK(hipEventSynchronize(c.cc_ev[k]), "ccmul staging");
     std::memcpy(c.cc_pin[k], tl.data(), bytes);
     HIPCHK(hipMemcpyAsync(d_tl, c.cc_pin[k], bytes, hipMemcpyHostToDevice, st), "ccmul term lists");
     HIPCHK(hipEventRecord(c.cc_ev[k], st), "ccmul staging");

@@ -12,14 +12,17 @@ namespace he {
 template <class A>
 struct MacAcc;
 
-// fp64: each product has |p| <= 0.76 q; after a fold |acc| <= 0.51 q, so a chunk
-// of 8 products keeps |acc| <= 6.6 q < 7 q.
+// fp64: each product of two canonical residues has |p| <= mulv_out(1) = 0.885 q;
+// after a fold |acc| <= 0.51 q, so a chunk of 7 products keeps |acc| <= 6.71 q < 7 q.
 template <>
 struct MacAcc<ArF64> {
-  static constexpr int kChunk = 8;
+  static constexpr int kChunk = 7;
   static constexpr int kLoadBatch = 32;   // coefficients whose operands are loaded together
-  static constexpr bool kLoneReduced = true;   // one product, unfolded, has |p| <= 0.76 q
-  static constexpr int kOutBoundX100 = 76;     // bound of value(): a lone product or a fold
+  static constexpr bool kLoneReduced = true;   // one product, unfolded, has |p| <= 0.885 q
+  static constexpr int kOutBoundX100 = 89;     // bound of value(): a lone product or a fold
+  static_assert(ArF64::kReduced + kChunk * ArF64::mulv_out(1.0) <= ArF64::kLimit, "chunk exceeds the fp64 bound");
+  static_assert(kOutBoundX100 >= 100.0 * ArF64::mulv_out(1.0) && kOutBoundX100 >= 100.0 * ArF64::kReduced,
+                "value() bound understated");
   double acc = 0.0;
   __device__ __forceinline__ void set(const ArF64 &ar, uint64_t a, uint64_t b) { acc = ar.mulv(ar.load(a), ar.load(b)); }
   __device__ __forceinline__ void add(const ArF64 &ar, uint64_t a, uint64_t b) { acc += ar.mulv(ar.load(a), ar.load(b)); }

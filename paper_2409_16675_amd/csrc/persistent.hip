@@ -257,10 +257,13 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
   }
 }
 
-// Zero the queue head, the error flag and the per-job counters (a kernel, not a
-// memset, so that the launch can be captured into a graph and replayed).
-__global__ void k_reset_ctl(uint32_t *ctl, uint32_t n_words) {
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_words; k += gridDim.x * blockDim.x) ctl[k] = 0u;
+// Zero the queue heads and the per-job counters (a kernel, not a memset, so
+// that the launch can be captured into a graph and replayed).  The error flag
+// is cleared only with clear_err: a batch keeps it set across runs until its
+// sync reports it, so a failed wait of any queued run is not lost.
+__global__ void k_reset_ctl(uint32_t *ctl, uint32_t n_words, uint32_t clear_err) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_words; k += gridDim.x * blockDim.x)
+    if (k != CTL_ERR || clear_err) ctl[k] = 0u;
 }
 
 // Cache maintenance around a persistent launch, which may be a graph replay whose
@@ -316,8 +319,8 @@ bool persistent_variant(int arith, uint32_t logn_min, uint32_t logn_max, int pre
 
 hipError_t launch_persistent(const PVariant &v, const PTask *tasks, uint32_t n_tasks, const XQ &xq, const PJob *jobs,
                              uint32_t n_jobs, uint32_t *ctl, uint32_t ctl_words, uint32_t grid, uint32_t spin_limit,
-                             uint32_t strict, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ctl, ctl_words);
+                             uint32_t strict, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool clear_err) {
+  hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(256), 0, st, ctl, ctl_words, clear_err ? 1u : 0u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_edge_fence, dim3(64), dim3(64), 0, st, 0);

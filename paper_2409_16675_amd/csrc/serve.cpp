@@ -260,7 +260,8 @@ static void server_loop(he_server *S) {
           const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>((size_t)cus * v.wg_per_cu, tasks.size()));
           if (e == hipSuccess)
             e = launch_persistent(v, sl.d_tasks, (uint32_t)tasks.size(), xq, sl.d_jobs, (uint32_t)pjobs.size(), sl.d_ctl,
-                                  CTL_DONE + (uint32_t)pjobs.size(), grid, kSpinLimit, 0, sl.st);
+                                  CTL_DONE + (uint32_t)pjobs.size(), grid, kSpinLimit, 0, sl.st, nullptr, nullptr,
+                                  true);
           if (e == hipSuccess) e = hipMemcpyAsync(sl.h_err, sl.d_ctl + CTL_ERR, 4, hipMemcpyDeviceToHost, sl.st);
         }
       }

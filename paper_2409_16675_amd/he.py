@@ -24,6 +24,7 @@ HE_EINVAL, HE_EUNSUPPORTED, HE_ENOMEM, HE_EDEVICE, HE_ERANGE, HE_EBUSY, HE_ETIME
 HE_ARITH_AUTO, HE_ARITH_F64, HE_ARITH_U64 = 0, 1, 2
 HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC, HE_KIND_DX = 0, 1, 2, 3
+HE_PREPARE_PPMUL, HE_PREPARE_CCMUL = 0x1, 0x2
 
 c_void_p, c_u32, c_u64, c_i32, c_size = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
 u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -76,6 +77,8 @@ _SIGS = {
                               c_void_p],
     "he_expand_c1": [c_void_p, u64p, c_u32, c_u32, c_void_p, c_void_p],
     "he_ppmul": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
+    "he_ctx_prepare": [c_void_p, c_u32, c_u32, c_u32],
+    "he_keygen": [c_void_p, c_u64, c_void_p],
     "he_pack_input": [c_void_p, i32p, i64p],
     "he_extract_output": [c_void_p, i64p, i64p],
     "he_encrypt": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -87,6 +90,7 @@ _SIGS = {
     "he_batch_rebind": [c_void_p, c_u32, c_void_p],
     "he_batch_run": [c_void_p, c_void_p],
     "he_batch_sync": [c_void_p, c_void_p],
+    "he_batch_set_spin_limit": [c_void_p, c_u32],
     "he_batch_get_info": [c_void_p, c_void_p],
     "he_batch_destroy": [c_void_p],
     "he_server_create": [c_void_p, ctypes.POINTER(c_void_p)],
@@ -301,6 +305,19 @@ def he_expand_c1(ctx, seed, first_ct, n_ct, out, stream=None):
     _chk(_lib.he_expand_c1(ctx, ps, first_ct, n_ct, _ptr(out), _stream(stream)), "he_expand_c1")
 
 
+def he_ctx_prepare(ctx, ops, ccmul_max_out=0, ccmul_max_terms=0):
+    """Build the resources of he_ppmul / he_ccmul ahead of their calls (HE_PREPARE_* bits)."""
+    _chk(_lib.he_ctx_prepare(ctx, ops, ccmul_max_out, ccmul_max_terms), "he_ctx_prepare")
+
+
+def he_keygen(ctx, seed):
+    """Ternary secret key [N] (int8, host) from a 64-bit seed."""
+    N = he_ctx_info(ctx)[0]
+    sk = np.zeros(N, dtype=np.int8)
+    _chk(_lib.he_keygen(ctx, seed, sk.ctypes.data), "he_keygen")
+    return sk
+
+
 def he_ppmul_ws_size(plan, flags=0):
     b = c_size()
     _chk(_lib.he_ppmul_ws_size(plan, flags, ctypes.byref(b)), "he_ppmul_ws_size")
@@ -420,6 +437,10 @@ def he_batch_run(b, stream=None):
 
 def he_batch_sync(b, stream=None):
     _chk(_lib.he_batch_sync(b, _stream(stream)), "he_batch_sync")
+
+
+def he_batch_set_spin_limit(b, polls):
+    _chk(_lib.he_batch_set_spin_limit(b, polls), "he_batch_set_spin_limit")
 
 
 def he_batch_get_info(b):

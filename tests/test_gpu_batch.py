@@ -202,3 +202,30 @@ def test_profiled_direct_launches(gpu_lib, ctxs):
     for k, j in enumerate(jobs):
         assert_equal_u64(he.to_numpy_u64(j["out"]), expect[k], "profiled job %d" % k)
     he.he_batch_destroy(b)
+
+
+@pytest.mark.gpu
+def test_timed_out_wait_is_reported_after_a_later_run(gpu_lib, ctxs):
+    # a spin limit of 0 makes every dependency wait give up at its first poll
+    # (forced from the host: the kernel still finishes every task); the error
+    # flag must survive the next, normal run and be reported by the sync, once
+    he = gpu_lib
+    jobs = [make_job(he, ctxs, 0, 1, 450 + k) for k in range(2)]   # conv 3->16 @32x32, N = 8192
+    expect = [oracle_out(j) for j in jobs]
+    b = he.he_batch_create(0)
+    for j in jobs:
+        he.he_batch_add(b, j["ctx"].h, j["plan"].h, j["d_ct"], j["d_w"], j["out"], 0)
+    he.he_batch_build(b, 0)                     # direct launches read the limit at each run
+    he.he_batch_set_spin_limit(b, 0)
+    he.he_batch_run(b)
+    he.he_batch_set_spin_limit(b, 1 << 20)
+    he.he_batch_run(b)
+    with pytest.raises(he.HeError) as ei:
+        he.he_batch_sync(b)
+    assert ei.value.status == he.HE_ETIMEOUT
+    # reported once: the second run's outputs are right and the next sync is clean
+    for k, j in enumerate(jobs):
+        assert_equal_u64(he.to_numpy_u64(j["out"]), expect[k], "job %d after the normal run" % k)
+    he.he_batch_run(b)
+    he.he_batch_sync(b)
+    he.he_batch_destroy(b)

@@ -46,6 +46,7 @@ def _boundary(ctx, ct):
 
 def _run(he, ctx, a, b, row, ai, bi, n_out, rlk_hat, flags=0):
     n_terms = len(ai) if row is not None else a.shape[0]
+    he.he_ctx_prepare(ctx.h, he.HE_PREPARE_CCMUL, n_out, n_terms)
     ws = he.workspace(he.he_ccmul_ws_size(ctx.h, a.shape[0], b.shape[0], n_out, n_terms, flags))
     out = he.empty_u64((n_out, 2, ctx.L, ctx.N))
     he.he_ccmul(ctx.h, he.to_device_u64(a), a.shape[0], he.to_device_u64(b), b.shape[0], row, ai, bi, n_out, rlk_hat,
@@ -114,6 +115,7 @@ def test_back_to_back_calls_with_different_term_lists(gpu_lib):
              ([0, 3], [2, 2, 1], [0, 1, 3]),
              ([0, 1, 2, 3, 5], [1, 0, 3, 2, 2], [1, 2, 0, 3, 0])]
     runs = []
+    he.he_ctx_prepare(ctx.h, he.HE_PREPARE_CCMUL, 4, 5)
     print("case ccmul back-to-back N=%d L=%d" % (N, L), flush=True)
     for row, ai, bi in lists:
         n_out = len(row) - 1
@@ -177,8 +179,23 @@ def test_ccmul_errors(gpu_lib):
     # eight 50-bit primes would need nine auxiliary ones: refused
     ctx8 = he.Context(1024, 8)
     with pytest.raises(he.HeError) as ei:
-        he.he_ccmul_ws_size(ctx8.h, 1, 1, 1, 1)
+        he.he_ctx_prepare(ctx8.h, he.HE_PREPARE_CCMUL, 1, 1)
     assert ei.value.status == he.HE_EUNSUPPORTED
+    # a context whose product was never prepared: refused, nothing built by the call
+    ctx_np = he.Context(1024, 2)
+    with pytest.raises(he.HeError) as ei:
+        he.he_ccmul_ws_size(ctx_np.h, 1, 1, 1, 1)
+    assert ei.value.status == he.HE_EINVAL
+    # term lists larger than the staging was prepared for: refused
+    he.he_ctx_prepare(ctx_np.h, he.HE_PREPARE_CCMUL, 1, 1)
+    ap = synth.uniform_residues(synth.rng(96, synth.STREAM_CT), (2, 2), ctx_np.q, 1024)
+    wsz = he.he_ccmul_ws_size(ctx_np.h, 2, 2, 2, 2)
+    ws = he.workspace(wsz)
+    out = he.empty_u64((2, 2, 2, 1024))
+    with pytest.raises(he.HeError) as ei:
+        he.he_ccmul(ctx_np.h, he.to_device_u64(ap), 2, he.to_device_u64(ap), 2, None, None, None, 2, rlk_hat, out, 0,
+                    ws, ws.numel())
+    assert ei.value.status == he.HE_EINVAL
     bad = a.copy()
     bad[1, 0, 0, 3] = ctx.q[0]                             # not canonical
     with pytest.raises(he.HeError) as ei:

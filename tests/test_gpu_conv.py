@@ -35,8 +35,8 @@ def run_layer(he, ctx, plan, ct_in, plain_arr, flags=0):
     return he.to_numpy_u64(out)
 
 
-def conv_case(he, N, L, B, C, M, H, W, h, P, seed, flags=0, decrypt_check=2):
-    ctx = he.Context(N, L)
+def conv_case(he, N, L, B, C, M, H, W, h, P, seed, flags=0, decrypt_check=2, bits=50):
+    ctx = he.Context(N, L, prime_bits=bits)
     g = packing.ConvGeometry(C, H, W, h, P, N)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=W, h=h, P=P)
     info = plan.info

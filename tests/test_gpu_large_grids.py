@@ -80,6 +80,7 @@ def test_ccmul_conversions_past_65535_rows(gpu_lib):
     row = np.arange(n_out + 1, dtype=np.int32)
     ai = (np.arange(n_out) % 2).astype(np.int32)
     bi = ((np.arange(n_out) // 2) % 2).astype(np.int32)
+    he.he_ctx_prepare(ctx.h, he.HE_PREPARE_CCMUL, n_out, n_out)
     ws = he.workspace(he.he_ccmul_ws_size(ctx.h, 2, 2, n_out, n_out, 0))
     out = he.empty_u64((n_out, 2, L, N))
     he.he_ccmul(ctx.h, he.to_device_u64(a), 2, he.to_device_u64(a), 2, row, ai, bi, n_out, rlk_hat, out, 0, ws,

@@ -27,6 +27,7 @@ def _oracle_ppmul(a, b, row, cti, pti):
 def _ppmul(he, ctx, plan, a, b, flags=0):
     info = plan.info
     out = he.empty_u64((info["n_ct_out"], ctx.N))
+    he.he_ctx_prepare(ctx.h, he.HE_PREPARE_PPMUL)
     ws = he.workspace(he.he_ppmul_ws_size(plan.h, flags))
     he.he_ppmul(ctx.h, plan.h, he.to_device_u64(a), he.to_device_u64(b), out, flags, ws, ws.numel())
     torch.cuda.synchronize()
@@ -153,3 +154,23 @@ def test_online_protocol_end_to_end(gpu_lib):
             y = y.reshape(B, M, H + 2 * P - h + 1, -1)[0, 0]
             ref = plain.mod_t(plain.conv2d(x[b], w[m:m + 1], P)[0], T)
             assert np.array_equal(np.remainder(y, T), ref), (b, m)
+
+
+@pytest.mark.gpu
+def test_keygen_matches_oracle_and_decrypts(gpu_lib):
+    # the library's key generator (host) against the oracle's, and a key it made
+    # decrypting the library's encryption
+    he = gpu_lib
+    ctx = he.Context(1024, 2)
+    for seed in (0, 7, 2 ** 63 + 5):
+        assert np.array_equal(he.he_keygen(ctx.h, seed), bfv.keygen(seed, 1024)), seed
+    s = he.he_keygen(ctx.h, 99)
+    m = synth.uniform_mod_t(synth.rng(98, synth.STREAM_PT), (1024,))
+    a = synth.uniform_residues(synth.rng(98, synth.STREAM_A), (), ctx.q, 1024)
+    e = synth.small_error(synth.rng(98, synth.STREAM_E), 1024)
+    ct = he.empty_u64((2, 2, 1024))
+    sd = torch.from_numpy(s).cuda()
+    he.he_encrypt(ctx.h, sd, torch.from_numpy(m.astype(np.int64)).cuda(), he.to_device_u64(a),
+                  torch.from_numpy(e.astype(np.int32)).cuda(), ct)
+    torch.cuda.synchronize()
+    assert np.array_equal(bfv.decrypt(he.to_numpy_u64(ct), s, ctx.q, ctx.psi, T), m.astype(np.int64))

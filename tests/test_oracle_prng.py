@@ -74,3 +74,25 @@ def test_encryption_with_a_regenerated_c1_decrypts():
     ct = bfv.encrypt(m, s, a, e, q, psi, T)
     assert np.array_equal(ct[1], a)
     assert np.array_equal(bfv.decrypt(ct, s, q, psi, T), m)
+
+
+def test_ternary_map_splits_the_words_in_thirds():
+    third = (1 << 64) // 3                      # 2^64 = 3 * third + 1
+    assert bfv.ternary_from_word(0) == -1
+    assert bfv.ternary_from_word(third) == -1   # 3 * third < 2^64
+    assert bfv.ternary_from_word(third + 1) == 0
+    assert bfv.ternary_from_word(2 * third) == 0      # 3 * 2 * third = 2^65 - 2
+    assert bfv.ternary_from_word(2 * third + 1) == 1  # 3 * (2 * third + 1) = 2^65 + 1
+    assert bfv.ternary_from_word((1 << 64) - 1) == 1
+
+
+def test_keygen_is_numpy_philox_mapped_to_ternary():
+    sk = bfv.keygen(0xC0FFEE, 64)
+    for k in (0, 1, 17, 63):
+        w = _numpy_block((k, 0, 0, (1 << 64) - 1), (0xC0FFEE, 0))[0]
+        assert int(sk[k]) == bfv.ternary_from_word(w)
+    big = bfv.keygen(12345, 3000)
+    assert set(np.unique(big).tolist()) <= {-1, 0, 1}
+    counts = np.array([(big == v).sum() for v in (-1, 0, 1)])
+    assert (np.abs(counts - 1000) < 130).all()   # about 4.5 sigma of a binomial(3000, 1/3)
+    assert not np.array_equal(bfv.keygen(1, 64), bfv.keygen(2, 64))
