@@ -241,6 +241,22 @@ he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes);
 he_status he_corr_conv2d(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in, const void *plain,
                          uint64_t *ct_out, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
+/* he_corr_conv2d for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the workspace taken from a fixed device array of
+ * the library, HE_NOALLOC_SCRATCH_MB MiB per GPU, held from the library's
+ * first use of that GPU until the process ends.  No hipMalloc, hipFree or
+ * other allocating call; kernel timing (he_ctx_profile) is skipped for it.
+ * Arguments as he_corr_conv2d without ws/ws_bytes.  HE_ENOMEM if the layer's
+ * he_workspace_size(flags) exceeds the array; HE_EINVAL for HE_VALIDATE
+ * (it synchronises the stream).  Every call on one GPU shares that GPU's
+ * array (nothing in it needs to start at zero: each call writes what it
+ * reads), so calls that overlap on one GPU -- on different streams or from
+ * different threads -- race and must be serialised by the caller. */
+#define HE_NOALLOC_SCRATCH_MB 64
+he_status he_corr_conv2d_noalloc(he_ctx *ctx, const he_plan *plan, const uint64_t *ct_in, const void *plain,
+                                 uint64_t *ct_out, uint32_t flags, void *stream);
+
 /* Seeded component c1 (Section 7, Discussion: the client sends a seed instead of the
  * uniform c1; about half the upload).  Coefficient k of component 1 of
  * ciphertext j at prime i is (w0 2^64 + w1) mod q_i, where (w0, w1, w2, w3) is

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libhe.so")
 
 # longest compiles first: the pool of workers starts them together
 SOURCES = ["persistent.hip", "ccmul.hip", "ring_13.hip", "ring_12.hip", "ring_11.hip", "ring_14.hip", "ring_10.hip",
-           "kernels.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp",
+           "kernels.hip", "noalloc.hip", "context.cpp", "plan.cpp", "capi.cpp", "bfv_host.cpp", "batch.cpp", "tune.cpp", "serve.cpp",
            "ccmul.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

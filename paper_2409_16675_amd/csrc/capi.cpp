@@ -9,6 +9,7 @@ he_status client_decrypt_crt(const Ctx &c, const uint64_t *x, uint32_t n_ct, int
 he_status ccmul_prepare(Ctx &c, uint32_t max_out, uint32_t max_terms);
 
 static thread_local std::string g_err;
+thread_local bool g_untimed = false;
 void set_error(const std::string &msg) { g_err = msg; }
 he_status fail(he_status st, const std::string &msg) {
   g_err = msg;

@@ -71,9 +71,13 @@ he_status validate(const Ctx &c, const uint64_t *planes, size_t n_planes, void *
 enum KernelKind { KK_FWD = 0, KK_FWD_LIFT = 1, KK_INV = 2, KK_MAC_INV = 3, KK_MAC = 4, KK_PACK = 5, KK_PERSIST = 6, KK_RNS = 7 };
 
 // Bracket one launch with events when profiling is on: returns the launch's error.
+// Set on a thread while a call that must not allocate runs: kernel timing
+// (which creates events) is skipped for its launches.
+extern thread_local bool g_untimed;
+
 template <class F>
 hipError_t timed(const Ctx &c, hipStream_t st, int kind, F &&launch) {
-  if (!c.prof_on) return launch();
+  if (!c.prof_on || g_untimed) return launch();
   Ctx::ProfRec r{kind, nullptr, nullptr};
   hipError_t e = hipEventCreate(&r.a);
   if (e == hipSuccess) e = hipEventCreate(&r.b);

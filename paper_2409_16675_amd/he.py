@@ -25,6 +25,7 @@ HE_ARITH_AUTO, HE_ARITH_F64, HE_ARITH_U64 = 0, 1, 2
 HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC, HE_KIND_DX = 0, 1, 2, 3
 HE_PREPARE_PPMUL, HE_PREPARE_CCMUL = 0x1, 0x2
+HE_NOALLOC_SCRATCH_MB = 64
 
 c_void_p, c_u32, c_u64, c_i32, c_size = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
 u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -72,6 +73,7 @@ _SIGS = {
     "he_plan_terms": [c_void_p, i32p, i32p, i32p],
     "he_workspace_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
     "he_corr_conv2d": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p, c_size, c_void_p],
+    "he_corr_conv2d_noalloc": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p],
     "he_ppmul_ws_size": [c_void_p, c_u32, ctypes.POINTER(c_size)],
     "he_corr_conv2d_seeded": [c_void_p, c_void_p, c_void_p, u64p, c_void_p, c_void_p, c_u32, c_void_p, c_size,
                               c_void_p],
@@ -286,6 +288,12 @@ def he_workspace_size(plan, flags=0):
 def he_corr_conv2d(ctx, plan, ct_in, plain, ct_out, flags=0, ws=None, ws_bytes=0, stream=None):
     _chk(_lib.he_corr_conv2d(ctx, plan, _ptr(ct_in), _ptr(plain), _ptr(ct_out), flags, _ptr(ws), ws_bytes,
                              _stream(stream)), "he_corr_conv2d")
+
+
+def he_corr_conv2d_noalloc(ctx, plan, ct_in, plain, ct_out, flags=0, stream=None):
+    """he_corr_conv2d with the library's fixed device scratch instead of a workspace (allocates nothing)."""
+    _chk(_lib.he_corr_conv2d_noalloc(ctx, plan, _ptr(ct_in), _ptr(plain), _ptr(ct_out), flags, _stream(stream)),
+         "he_corr_conv2d_noalloc")
 
 
 def _seed(seed):
