@@ -125,11 +125,13 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
     const size_t before = tasks.size();
     if (!(bj.job.flags & HE_IN_NTT)) {
       const uint32_t planes = in.n_ct_in * 2 * L;
-      for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p)});
+      for (uint32_t p = 0; p < planes; p += G)
+        tasks.push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p), 0, -1, 0, 0});
       info.fwd_planes += planes;
     }
     const uint32_t pplanes = in.n_pt * L;
-    for (uint32_t p = 0; p < pplanes; p += G) tasks.push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p)});
+    for (uint32_t p = 0; p < pplanes; p += G)
+      tasks.push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p), 0, -1, 0, 0});
     info.fwd_planes += pplanes;
     pjobs[j].n_pre = (uint32_t)(tasks.size() - before);
     info.cpmul += in.n_terms;
@@ -139,14 +141,23 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
     const JobRef &bj = jobs[j];
     const uint32_t G = slab_n >> bj.ctx->logN, L = bj.ctx->L;
     const uint32_t planes = bj.plan->info.n_ct_out * 2 * L;
+    const uint32_t kind = PT_MAC_INV | (pjobs[j].n_pre ? PT_WAIT : 0u);
     if (G == 1) {
       // one plane per task: prime-major order (plane (o * 2 + comp) * L + i
       // for i, then o, then comp), so that the operands and twiddles an XCD
       // works on at a time are those of one prime and stay in its L2
+      const Plan &pl = *bj.plan;
       for (uint32_t i = 0; i < L; ++i)
-        for (uint32_t oc = 0; oc < planes / L; ++oc) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, oc * L + i, 1u});
+        for (uint32_t oc = 0; oc < planes / L; ++oc) {
+          const uint32_t o = oc / 2, comp = oc % 2;
+          const int32_t t0 = pl.row[o], t1 = pl.row[o + 1];
+          const uint32_t a0 = t1 > t0 ? ((uint32_t)pl.cti[t0] * 2 + comp) * L + i : 0u;
+          const uint32_t b0 = t1 > t0 ? (uint32_t)pl.pti[t0] * L + i : 0u;
+          tasks.push_back(PTask{kind, (uint32_t)j, oc * L + i, 1u, t0, t1, a0, b0});
+        }
     } else {
-      for (uint32_t p = 0; p < planes; p += G) tasks.push_back(PTask{PT_MAC_INV, (uint32_t)j, p, std::min(G, planes - p)});
+      for (uint32_t p = 0; p < planes; p += G)
+        tasks.push_back(PTask{kind, (uint32_t)j, p, std::min(G, planes - p), 0, -1, 0, 0});
     }
     info.inv_planes += planes;
   }

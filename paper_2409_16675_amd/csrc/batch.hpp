@@ -16,8 +16,17 @@ constexpr int kXcds = 8;
 // the error flag (about 1 s at the longest back-off)
 constexpr uint32_t kSpinLimit = 1u << 20;
 
+// A task: planes [first, first + count) of the job's array.  kind carries
+// PT_WAIT when the job has pre tasks that a dependent task must wait for.  A
+// multiply-accumulate task of one plane also carries its output's term range
+// [t0, t1) and the planes of its first term's operands (a0 in the transformed
+// inputs, b0 in the transformed plaintexts), so it starts its operand loads
+// without reading the term lists; t1 < 0: read them (several planes per task).
+enum : uint32_t { PT_KIND_MASK = 0xFFu, PT_WAIT = 0x100u };
 struct PTask {
-  uint32_t kind, job, first, count;   // planes [first, first + count) of the job's array
+  uint32_t kind, job, first, count;
+  int32_t t0, t1;
+  uint32_t a0, b0;
 };
 
 struct PJob {

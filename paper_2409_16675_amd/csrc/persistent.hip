@@ -51,7 +51,8 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   const uint32_t i = valid ? plane % L : 0;
   const PrimeK pk = jb.primes[i];
   const A ar(pk);
-  if (tk.kind == PT_FWD_CT) {
+  const uint32_t kind = tk.kind & PT_KIND_MASK;
+  if (kind == PT_FWD_CT) {
     const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
     auto ld = [&](int k) { return ar.load(valid ? src[(uint32_t)k] : 0ull); };
@@ -59,7 +60,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       if (valid) dst[(uint32_t)k] = v;
     };
     ntt_forward<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
-  } else if (tk.kind == PT_PT) {
+  } else if (kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
     auto st = [&](int k, uint64_t v) {
@@ -84,8 +85,14 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     }
   } else {   // PT_MAC_INV: output plane (o, comp, i)
     const uint32_t comp = (plane / L) & 1, o = plane / (2 * L);
+    // a one-plane task carries its term range and its first term's operand
+    // planes: the operand loads start without a read of the term lists
+    const bool listed = tk.t1 >= 0;
     int t0 = 0, t1 = 0;
-    if (valid) {
+    if (listed) {
+      t0 = tk.t0;
+      t1 = tk.t1;
+    } else if (valid) {
       t0 = as_global(jb.row)[o];
       t1 = as_global(jb.row)[o + 1];
     }
@@ -93,14 +100,24 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     const HE_GLOBAL uint64_t *ct_hat = as_global((const uint64_t *)jb.ct_hat), *pt_hat = as_global((const uint64_t *)jb.pt_hat);
     MacAcc<A> acc[G::E];
     auto operands = [&](int t) {
-      const HE_GLOBAL uint64_t *a = ct_hat + ((size_t)(cti[t] * 2 + comp) * L + i) * G::N;
-      const HE_GLOBAL uint64_t *b = pt_hat + ((size_t)pti[t] * L + i) * G::N;
+      uint32_t pa, pb;
+      if (listed && t == t0) {
+        pa = tk.a0;
+        pb = tk.b0;
+      } else {
+        pa = ((uint32_t)cti[t] * 2 + comp) * L + i;
+        pb = (uint32_t)pti[t] * L + i;
+      }
+      const HE_GLOBAL uint64_t *a = ct_hat + (size_t)pa * G::N;
+      const HE_GLOBAL uint64_t *b = pt_hat + (size_t)pb * G::N;
       return std::pair<const HE_GLOBAL uint64_t *, const HE_GLOBAL uint64_t *>(a, b);
     };
     mac_terms<A, G::E>(ar, pk, acc, t0, t1, operands, [&](int e) { return slot_index<G, G::NPASS - 1>(tid_g, e); });
     V v[G::E];
 #pragma unroll
     for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
+    // (the first pass's twiddles are loaded here, not with the operands: held
+    // across the products they would push the kernel past its register budget)
     const auto twi = PTw<A>::inv(jb) + (size_t)i * G::N;
     PassTw<A, G, G::NPASS - 1, true> first;
     first.load(twi, tid_g);
@@ -149,7 +166,7 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     const PTask *__restrict__ tasks, uint32_t n_tasks, XQ xq, const PJob *__restrict__ jobs, uint32_t n_jobs,
     uint32_t *__restrict__ ctl, uint32_t spin_limit, uint32_t strict) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_task, s_wait;
+  __shared__ uint32_t s_task[2], s_wait[2];   // used in turn by consecutive iterations
   __shared__ uint32_t s_ready[64];   // acquired jobs (bitmap, jobs < 2048); touched by thread 0 only
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
   const int tid = threadIdx.x;
@@ -161,7 +178,10 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
   // Task source: the shared queue of pre tasks [0, xq.b[0]) first; then this
   // XCD's queue of dependent tasks (workgroups are dealt round-robin over the
   // XCDs, so blockIdx % 8 is the XCD), then the other XCDs' queues in turn.
-  // Thread 0 keeps the following task in flight while the current one runs.
+  // Thread 0 looks two tasks ahead: the next task's index, kind and job are
+  // known (loaded while the current task ran) and the one after is grabbed
+  // while the current task runs, so deciding on a dependency wait reads no
+  // memory.
   const uint32_t my_xcd = blockIdx.x % kXcds;
   uint32_t q = 0;            // 0: pre queue; 1..8: dependent queue (my_xcd + q - 1) % 8
   auto grab = [&]() -> uint32_t {
@@ -178,29 +198,39 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     }
     return n_tasks;
   };
-  uint32_t next = 0;
-  if (tid == 0) next = grab();
-  for (;;) {
+  uint32_t n1 = n_tasks, n2 = n_tasks, k1 = 0, j1 = 0;
+  if (tid == 0) {
+    n1 = grab();
+    if (n1 < n_tasks) {
+      k1 = tasks[n1].kind;
+      j1 = tasks[n1].job;
+      n2 = grab();
+    }
+  }
+  for (uint32_t it = 0;; it ^= 1u) {
     // thread 0 takes the next task and decides, for the whole workgroup, whether
-    // it must wait for the job's pre tasks (so every thread takes the same branch)
+    // it must wait for the job's pre tasks (so every thread takes the same
+    // branch).  The slot of iteration it is written again two iterations later,
+    // after the barrier that every thread reaches only after reading it here.
     if (tid == 0) {
-      const uint32_t t0 = next;
-      if (t0 < n_tasks) next = grab();
-      uint32_t w = 0;
-      if (t0 < n_tasks) {
-        const PTask k0 = tasks[t0];
-        if (k0.kind == PT_MAC_INV && jobs[k0.job].n_pre)
-          w = (!(strict & 1u) && k0.job < 2048 && ((s_ready[k0.job >> 5] >> (k0.job & 31)) & 1u)) ? 0u : 1u;
+      const uint32_t t0 = n1, kind0 = k1, job0 = j1;
+      n1 = n2;
+      if (n1 < n_tasks) {
+        k1 = tasks[n1].kind;
+        j1 = tasks[n1].job;
+        n2 = grab();
       }
-      s_task = t0;
-      s_wait = w;
+      uint32_t w = 0;
+      if (t0 < n_tasks && (kind0 & PT_WAIT))
+        w = (!(strict & 1u) && job0 < 2048 && ((s_ready[job0 >> 5] >> (job0 & 31)) & 1u)) ? 0u : 1u;
+      s_task[it] = t0;
+      s_wait[it] = w;
     }
     __syncthreads();
     // the task index and the wait decision are workgroup-uniform: keep them (and
     // the task and job fields loaded through them) in scalar registers
-    const uint32_t t = __builtin_amdgcn_readfirstlane(s_task);
-    const uint32_t must_wait = __builtin_amdgcn_readfirstlane(s_wait);
-    __syncthreads();
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_task[it]);
+    const uint32_t must_wait = __builtin_amdgcn_readfirstlane(s_wait[it]);
     if (t >= n_tasks) break;
     const PTask tk = tasks[t];
     const PJob &jb = jobs[tk.job];
@@ -245,15 +275,16 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
           break;
       }
     }
-    if (tk.kind != PT_MAC_INV) {
+    if ((tk.kind & PT_KIND_MASK) != PT_MAC_INV) {
       // every wave waits until its own global stores have reached L2 (the barrier
       // alone orders LDS only); thread 0's release then writes L2 back and publishes
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       if (strict & 1u) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0) __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (tk.kind != PT_MAC_INV && tid == 0)
-      __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // (a dependent task needs no barrier here: the next task touches the plane
+    // in LDS only after the next iteration's barrier)
   }
 }
 
