@@ -4,7 +4,7 @@
 Workload (one step): the server side of one conv2d forward layer -- batch 16 of
 3x32x32 integer activations packed with pi_x and encrypted, 16 output channels,
 3x3 kernel, stride 1, pad 1, int8 weights packed with pi_w; ring degree 8192,
-3 primes (50-bit); 256 CPMul-accumulates producing 256 output ciphertexts.
+3 primes (48-bit); 256 CPMul-accumulates producing 256 output ciphertexts.
 Every step transforms the 16 input ciphertexts, packs and transforms the 16
 weight polynomials, multiply-accumulates and inverse-transforms the outputs.
 
@@ -90,7 +90,7 @@ def workload(he, synth, torch, n_layers=1):
     weights drawn from their own seeded streams), inputs encrypted on the device."""
     N, L, B, C, M, H, W, h, P = 8192, 3, 16, 3, 16, 32, 32, 3, 1
     import numpy as np
-    ctx = he.Context(N, L, prime_bits=50)
+    ctx = he.Context(N, L, prime_bits=48)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=W, h=h, P=P)
     info = plan.info
     s = synth.ternary(synth.rng(2, synth.STREAM_SK), N)
@@ -113,7 +113,7 @@ def workload(he, synth, torch, n_layers=1):
     return dict(ctx=ctx, plan=plan, info=info, ct_in=layers[0]["ct_in"], w=layers[0]["w"], x=layers[0]["x"],
                 wh=layers[0]["wh"], layers=layers, N=N, L=L,
                 config=dict(workload="conv2d forward, batch 16 x 3x32x32 -> 16 channels, 3x3 kernel, stride 1, pad 1; "
-                                     "N=8192, 3 primes of 50 bits, t=65537; 256 CPMul-accumulates per step",
+                                     "N=8192, 3 primes of 48 bits, t=65537; 256 CPMul-accumulates per step",
                             batch=B, in_channels=C, out_channels=M, map=[H, W], kernel=h, pad=P, N=N, L=L,
                             cpmul_per_step=info["n_terms"]))
 

@@ -64,8 +64,8 @@ typedef struct he_server he_server;
 
 /* Arithmetic used inside the kernels.  Results are identical (canonical
  * residues); only speed and the admissible primes differ. */
-#define HE_ARITH_AUTO 0   /* F64 when every q_i < 2^50, else U64 */
-#define HE_ARITH_F64 1    /* exact products through fp64 FMA; needs q_i < 2^50 */
+#define HE_ARITH_AUTO 0   /* F64 when every q_i < 2^48, else U64 */
+#define HE_ARITH_F64 1    /* exact products through fp64 FMA; needs q_i < 2^48 */
 #define HE_ARITH_U64 2    /* Shoup products through 32-bit integer multiplies; q_i < 2^62 */
 
 typedef struct {
@@ -107,7 +107,7 @@ he_status he_ctx_prepare(he_ctx *ctx, uint32_t ops, uint32_t ccmul_max_out, uint
  * and log2 of the coefficients each thread holds (3, 4 or 5; the plane is split
  * over N >> loge threads, which must be 64..1024).  Every schedule returns the
  * same bytes; the autotuner picks the fastest.  HE_EUNSUPPORTED if not compiled
- * for this N or if F64 is asked with a prime >= 2^50. */
+ * for this N or if F64 is asked with a prime >= 2^48. */
 #define HE_OP_FWD 0   /* forward transforms (inputs and plaintexts) */
 #define HE_OP_INV 1   /* stand-alone inverse transforms */
 #define HE_OP_MAC 2   /* fused multiply-accumulate + inverse transform */
@@ -406,7 +406,7 @@ typedef struct {
 /* Create an empty batch for `device` (host memory only). */
 he_status he_batch_create(int32_t device, he_batch **out);
 /* Append a job; the plan and every buffer must stay valid while the batch is used.
- * All jobs of a batch must use the same arithmetic (all primes < 2^50, or not). */
+ * All jobs of a batch must use the same arithmetic (all primes < 2^48, or not). */
 he_status he_batch_add(he_batch *b, he_ctx *ctx, const he_job *job, uint32_t *index);
 /* Plan the task table, allocate the batch workspace and device tables, and
  * (with HE_BATCH_GRAPH) capture the launch into a graph.  Allocates device memory. */

@@ -6,10 +6,13 @@
 //         with two FMAs: h = fl(y*w), l = y*w - h (exact, one FMA), a quotient
 //         estimate k = rint(y * (w/q)), and r = (h - k*q) + l, where the FMA
 //         h - k*q is exact because the true difference is an integer below
-//         2^53.  With q < 2^50 and |y| <= B*q the quotient is off by at most
-//         1/2 + B/4, so |r| <= (1/2 + B/4) q.  Values stay signed and lazily
-//         reduced; every caller keeps |v| <= 7q (checked at compile time by
-//         the bound bookkeeping in ntt.hpp) so every integer is exact in fp64.
+//         2^53.  With q < 2^48 and |y| <= B*q the estimate y*fl(w/q) carries
+//         two roundings of |y w / q| < B 2^48, so the quotient is off by at
+//         most 1/2 + B/16 and |r| <= (1/2 + B/16) q.  Values stay signed and
+//         lazily reduced; every caller keeps |v| <= 31q < 2^53 (checked at
+//         compile time by the bound bookkeeping in ntt.hpp) so every integer
+//         is exact in fp64.  (Primes below 2^48 rather than 2^50 give 31q of
+//         headroom instead of 7q: the transforms reduce a quarter as often.)
 //         gfx950 issues v_fma_f64 / v_mul_f64 / v_rndne_f64 at full rate.
 //
 //  ArU64  residues held as uint64 in Harvey's lazy ranges, products by
@@ -53,14 +56,14 @@ struct ArF64 {
   double q, qinv;
 
   // Bound bookkeeping, in units of q (compile time).
-  static constexpr double kLimit = 7.0;
+  static constexpr double kLimit = 31.0;
   static constexpr double kCanon = 1.0;                 // canonical load
   static constexpr double kReduced = 0.51;              // after reduce()
-  static constexpr double mul_out(double b_in) { return 0.5 + 0.25 * b_in + 0.01; }
+  static constexpr double mul_out(double b_in) { return 0.5 + 0.0625 * b_in + 0.01; }
   // mulv forms the quotient companion in the kernel, fl(b * fl(1/q)), so the
-  // quotient estimate carries three roundings of |y b / q| <= b_in q < b_in 2^50:
-  // at most 3 * 2^-53 * b_in * 2^50 = 0.375 b_in, plus 1/2 from rint
-  static constexpr double mulv_out(double b_in) { return 0.5 + 0.375 * b_in + 0.01; }
+  // quotient estimate carries three roundings of |y b / q| <= b_in q < b_in 2^48:
+  // at most 3 * 2^-53 * b_in * 2^48 = 0.094 b_in, plus 1/2 from rint
+  static constexpr double mulv_out(double b_in) { return 0.5 + 0.09375 * b_in + 0.01; }
 
   __device__ __forceinline__ explicit ArF64(const PrimeK &p) : q(p.qd), qinv(p.qinv) {}
 

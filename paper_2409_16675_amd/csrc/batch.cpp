@@ -59,10 +59,16 @@ namespace he {
 
 static inline size_t al256b(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// bytes of the transformed plaintexts of a job
+static size_t pt_hat_bytes(const JobRef &j) {
+  const size_t plane = (size_t)j.ctx->L * j.ctx->N * 8;
+  return al256b((size_t)j.plan->info.n_pt * plane);
+}
+
 size_t job_ws_bytes(const JobRef &j) {
   const he_plan_info &in = j.plan->info;
   const size_t plane = (size_t)j.ctx->L * j.ctx->N * 8;
-  size_t b = al256b((size_t)in.n_pt * plane);
+  size_t b = pt_hat_bytes(j);
   if (!(j.job.flags & HE_IN_NTT)) b += al256b((size_t)in.n_ct_in * 2 * plane);
   return b;
 }
@@ -79,8 +85,8 @@ static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
   pj.tw_inv = arith == HE_ARITH_F64 ? c.d_tw_f64_inv : c.d_tw_u64_inv;
   pj.ct_in = bj.job.ct_in;
   pj.pt_hat = (uint64_t *)ws;
-  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in)
-                              : (uint64_t *)(ws + al256b((size_t)in.n_pt * plane));
+  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in) : (uint64_t *)(ws + pt_hat_bytes(bj));
+  pj.ct_f64 = (arith == HE_ARITH_F64 && !(f & HE_IN_NTT)) ? 1u : 0u;
   pj.plain = bj.job.plain;
   pj.ct_out = bj.job.ct_out;
   pj.row = p.d_row();
@@ -115,6 +121,8 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
   tasks.clear();
   pjobs.assign(nj, PJob{});
   info = he_batch_info{};
+  std::vector<std::vector<PTask>> pre(nj);
+  std::vector<uint32_t> n_dep_job(nj, 0);
   for (size_t j = 0; j < nj; ++j) {
     he_status s = fill_job(jobs[j], ws[j], arith, pjobs[j]);
     if (s != HE_OK) return s;
@@ -122,19 +130,43 @@ he_status build_tables(const std::vector<JobRef> &jobs, const std::vector<char *
     const he_plan_info &in = bj.plan->info;
     if ((uint32_t)bj.ctx->logN > (uint32_t)slab) return fail(HE_EUNSUPPORTED, "ring degree above the kernel slab");
     const uint32_t G = slab_n >> bj.ctx->logN, L = bj.ctx->L;
-    const size_t before = tasks.size();
     if (!(bj.job.flags & HE_IN_NTT)) {
       const uint32_t planes = in.n_ct_in * 2 * L;
       for (uint32_t p = 0; p < planes; p += G)
-        tasks.push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p), 0, -1, 0, 0});
+        pre[j].push_back(PTask{PT_FWD_CT, (uint32_t)j, p, std::min(G, planes - p), 0, -1, 0, 0});
       info.fwd_planes += planes;
     }
     const uint32_t pplanes = in.n_pt * L;
     for (uint32_t p = 0; p < pplanes; p += G)
-      tasks.push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p), 0, -1, 0, 0});
+      pre[j].push_back(PTask{PT_PT, (uint32_t)j, p, std::min(G, pplanes - p), 0, -1, 0, 0});
     info.fwd_planes += pplanes;
-    pjobs[j].n_pre = (uint32_t)(tasks.size() - before);
+    pjobs[j].n_pre = (uint32_t)pre[j].size();
     info.cpmul += in.n_terms;
+    const uint32_t oplanes = in.n_ct_out * 2 * L;
+    n_dep_job[j] = G == 1 ? oplanes : (oplanes + G - 1) / G;
+  }
+  // Pre tasks go first, ordered by how soon an XCD's queue of dependent tasks
+  // (below: the job-ordered dependent tasks cut into kXcds contiguous runs)
+  // reaches the job: each queue's first jobs get their inputs transformed
+  // first, so no XCD starts by waiting for a job whose transforms come last.
+  {
+    uint64_t n_dep_all = 0;
+    for (uint32_t d : n_dep_job) n_dep_all += d;
+    std::vector<std::pair<uint64_t, size_t>> order;
+    uint64_t s = 0;
+    for (size_t j = 0; j < nj; ++j) {
+      const uint64_t e = s + n_dep_job[j];
+      uint64_t soon = UINT64_MAX;
+      for (int x = 0; x < kXcds; ++x) {
+        const uint64_t a = n_dep_all * x / kXcds, b = n_dep_all * (x + 1) / kXcds;
+        if (s < b && e > a) soon = std::min(soon, std::max(s, a) - a);
+      }
+      order.emplace_back(soon, j);
+      s = e;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto &u, const auto &v) { return u.first < v.first; });
+    for (const auto &oj : order) tasks.insert(tasks.end(), pre[oj.second].begin(), pre[oj.second].end());
   }
   const uint32_t n_pre = (uint32_t)tasks.size();
   for (size_t j = 0; j < nj; ++j) {

@@ -42,7 +42,7 @@ struct PJob {
   uint32_t pkind;
   uint32_t M, C, h, O, S, Cw, cb;
   uint32_t n_in, n_out, n_iw, n_ow, in_ct;
-  uint32_t pad_;
+  uint32_t ct_f64;       // fp64 batch: ct_hat holds the batch's own doubles (not the caller's residues)
 };
 
 // One job as the task-table builder sees it.

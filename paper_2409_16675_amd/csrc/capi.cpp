@@ -98,7 +98,7 @@ he_status he_ctx_set_schedule(he_ctx *ctx, uint32_t op, uint32_t arith, uint32_t
   Sched n{(int)arith, (int)loge};
   if ((arith != HE_ARITH_F64 && arith != HE_ARITH_U64) || !sched_valid(ctx->c->logN, n))
     return fail(HE_EUNSUPPORTED, "schedule not compiled for this ring degree");
-  if (arith == HE_ARITH_F64 && !ctx->c->f64_ok) return fail(HE_EUNSUPPORTED, "fp64 arithmetic needs primes below 2^50");
+  if (arith == HE_ARITH_F64 && !ctx->c->f64_ok) return fail(HE_EUNSUPPORTED, "fp64 arithmetic needs primes below 2^48");
   *s = n;
   return HE_OK;
 }

@@ -148,9 +148,9 @@ he_status ext_ring_build(Ctx &c, Ctx **ec, const RnsConv **conv) {
       qmax = q > qmax ? q : qmax;
     }
     need += 1.0;   // margin for the double sums
-    // auxiliary primes: below 2^50 when the context runs the fp64 path, else as
+    // auxiliary primes: below 2^48 when the context runs the fp64 path, else as
     // wide as the widest prime of Q; 1 mod 2N, distinct from Q and from t
-    const uint32_t bits = c.f64_ok ? 50 : (uint32_t)(64 - __builtin_clzll(qmax));
+    const uint32_t bits = c.f64_ok ? 48 : (uint32_t)(64 - __builtin_clzll(qmax));
     const uint64_t m = 2ull * c.N;
     uint64_t cand = ((1ull << bits) - 1) / m * m + 1;
     if (cand >= (1ull << bits)) cand -= m;

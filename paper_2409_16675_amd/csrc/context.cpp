@@ -120,10 +120,10 @@ he_status build_context(const he_params *p, Ctx **out, uint32_t max_L) {
     }
   }
   c->f64_ok = true;
-  for (uint64_t q : c->q) c->f64_ok = c->f64_ok && q < (1ull << 50);
+  for (uint64_t q : c->q) c->f64_ok = c->f64_ok && q < (1ull << 48);
   if (p->arith == HE_ARITH_F64 && !c->f64_ok) {
     delete c;
-    return fail(HE_EUNSUPPORTED, "fp64 arithmetic needs every prime below 2^50");
+    return fail(HE_EUNSUPPORTED, "fp64 arithmetic needs every prime below 2^48");
   }
   c->arith = p->arith == HE_ARITH_AUTO ? (c->f64_ok ? HE_ARITH_F64 : HE_ARITH_U64) : (int)p->arith;
   const int loge = 4;

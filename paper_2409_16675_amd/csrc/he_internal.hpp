@@ -23,7 +23,7 @@ struct Ctx {
   uint64_t t = 0;
   int device = 0;
   int arith = HE_ARITH_U64;      // default policy
-  bool f64_ok = false;           // every q_i < 2^50
+  bool f64_ok = false;           // every q_i < 2^48
   std::vector<uint64_t> q, psi;
   std::vector<uint64_t> delta_mod;   // floor(Q / t) mod q_i
   // device tables

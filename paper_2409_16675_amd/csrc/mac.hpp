@@ -3,23 +3,25 @@
 // Sec. 3.3): acc[k] = sum_t ct_t[k] * pt_t[k] mod q, shared by the fused
 // multiply-accumulate + inverse-transform kernel and the persistent kernel.
 #pragma once
+#include <type_traits>
 #include <utility>
 
 #include "arith.hpp"
+#include "ntt.hpp"
 
 namespace he {
 
 template <class A>
 struct MacAcc;
 
-// fp64: each product of two canonical residues has |p| <= mulv_out(1) = 0.885 q;
-// after a fold |acc| <= 0.51 q, so a chunk of 7 products keeps |acc| <= 6.71 q < 7 q.
+// fp64: each product of two canonical residues has |p| <= mulv_out(1) = 0.604 q;
+// after a fold |acc| <= 0.51 q, so a chunk of 48 products keeps |acc| <= 29.5 q < 31 q.
 template <>
 struct MacAcc<ArF64> {
-  static constexpr int kChunk = 7;
+  static constexpr int kChunk = 48;
   static constexpr int kLoadBatch = 32;   // coefficients whose operands are loaded together
-  static constexpr bool kLoneReduced = true;   // one product, unfolded, has |p| <= 0.885 q
-  static constexpr int kOutBoundX100 = 89;     // bound of value(): a lone product or a fold
+  static constexpr bool kLoneReduced = true;   // one product, unfolded, has |p| <= 0.604 q
+  static constexpr int kOutBoundX100 = 61;     // bound of value(): a lone product or a fold
   static_assert(ArF64::kReduced + kChunk * ArF64::mulv_out(1.0) <= ArF64::kLimit, "chunk exceeds the fp64 bound");
   static_assert(kOutBoundX100 >= 100.0 * ArF64::mulv_out(1.0) && kOutBoundX100 >= 100.0 * ArF64::kReduced,
                 "value() bound understated");
@@ -111,6 +113,71 @@ __device__ __forceinline__ void mac_terms(const A &ar, const PrimeK &pk, MacAcc<
   if (run > 1 || !MacAcc<A>::kLoneReduced) {
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j].fold(ar, pk);
+  }
+}
+
+// Multiply-accumulate over fp64 operands that a batch keeps in its own format:
+// a from a plane of doubles reduced to |a| <= 0.51 q (A_U64: canonical
+// residues instead, for inputs the caller transformed), b from a plane of
+// doubles reduced to |b| <= 0.51 q.  A product is then 7 instructions (its
+// quotient companion fl(b fl(1/q)) formed in place) with no conversions; the
+// quotient estimate carries three roundings of |a b / q| <= 0.51 q < 0.51 2^48,
+// so |p| <= (1/2 + 3 * 0.51 / 32) q + slack.
+struct MacWsF64 {
+  static constexpr double kProdOut = 0.5 + 3.0 * 0.51 / 32.0 + 0.01;
+  static constexpr int kChunk = 48;        // products between folds
+  static constexpr int kLoadBatch = 32;    // coefficients whose operands are loaded together
+  static constexpr int kOutBoundX100 = 61;
+  static_assert(ArF64::kReduced + kChunk * kProdOut <= ArF64::kLimit, "chunk exceeds the fp64 bound");
+  static_assert(kOutBoundX100 >= 100.0 * kProdOut && kOutBoundX100 >= 100.0 * ArF64::kReduced, "bound understated");
+};
+
+// acc[e] = sum over terms t0 .. t1-1 of a_t[ix(e)] * b_t[ix(e)] (zero for an
+// empty range), folded every kChunk products and at the end unless a lone
+// product; operands(t) yields the two planes of term t.
+template <bool A_U64, int E, class Ops, class Ix>
+__device__ __forceinline__ void mac_terms_ws(const ArF64 &ar, double (&acc)[E], int t0, int t1, Ops operands, Ix ix) {
+  constexpr int B = E < MacWsF64::kLoadBatch ? E : MacWsF64::kLoadBatch;
+  // one term; the first sets the accumulators (no zero start, no add)
+  auto term = [&](auto first, int t) {
+    const auto [a, b] = operands(t);
+#pragma unroll
+    for (int j0 = 0; j0 < E; j0 += B) {
+      uint64_t va[B], vb[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const uint32_t k = ix(j0 + j);
+        va[j] = a[k];
+        vb[j] = b[k];
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const double x = A_U64 ? ar.load(va[j]) : __builtin_bit_cast(double, va[j]);
+        const double p = ar.mulv(x, __builtin_bit_cast(double, vb[j]));
+        if constexpr (decltype(first)::value) acc[j0 + j] = p;
+        else acc[j0 + j] += p;
+      }
+    }
+  };
+  if (t0 >= t1) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] = 0.0;
+    return;
+  }
+  term(std::true_type{}, t0);
+  int run = 1;   // products since the start or the last fold
+  for (int t = t0 + 1; t < t1; ++t) {
+    if (run == MacWsF64::kChunk) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) acc[j] = ar.reduce(acc[j]);
+      run = 0;
+    }
+    term(std::false_type{}, t);
+    ++run;
+  }
+  if (run > 1) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] = ar.reduce(acc[j]);
   }
 }
 

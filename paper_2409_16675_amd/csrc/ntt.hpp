@@ -560,7 +560,9 @@ __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typ
 }
 
 // Whole forward transform: ld2(t, c) reads coefficient t + c of the input
-// (coalesced pass-0 order), the result is written through st(i, canonical).
+// (coalesced pass-0 order), the result is written through st(i, canonical)
+// (CANON) or st(i, v) with v the policy's value (bounded by the last pass's
+// b_out, not reduced: for a caller that stores its own format).
 // The last pass has no low index bits: a thread's 2^R slots of a group are
 // consecutive coefficients and consecutive threads hold adjacent runs.  With
 // R <= 2 it writes the destination directly (no final round trip through
@@ -568,7 +570,7 @@ __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typ
 // With longer runs a store instruction would touch four times the lines of a
 // linear store, each a quarter filled, which measured slower than the round
 // trip: the pass goes to LDS and the plane is written in linear order.
-template <class A, class G, bool PF = true, class TwP, class Ld2, class St>
+template <class A, class G, bool PF = true, bool CANON = true, class TwP, class Ld2, class St>
 __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typename A::V *lds, Ld2 ld2, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
   using V = typename A::V;
@@ -588,20 +590,24 @@ __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typ
   }
   __syncthreads();
   if constexpr (!PF) last.load(tw, tid);
+  auto out = [&](int i, V v) {
+    if constexpr (CANON) st(i, ar.store(v));
+    else st(i, v);
+  };
   if constexpr (G::r(G::NPASS - 1) <= 2) {
-    auto st_out = [&](int t, int c, V v) { st(t + c, ar.store(v)); };
+    auto st_out = [&](int t, int c, V v) { out(t + c, v); };
     fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
   } else {
     fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, LdsPut<V>{lds}, [] {});
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < G::E; ++j) st(j * G::NT + tid, ar.store(lds[lin_lds<G>(tid, j)]));
+    for (int j = 0; j < G::E; ++j) out(j * G::NT + tid, lds[lin_lds<G>(tid, j)]);
   }
 }
 // The same with ld(i) reading coefficient i.
-template <class A, class G, bool PF = true, class TwP, class Ld, class St>
+template <class A, class G, bool PF = true, bool CANON = true, class TwP, class Ld, class St>
 __device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typename A::V *lds, Ld ld, St st) {
-  ntt_forward_tc<A, G, PF>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
+  ntt_forward_tc<A, G, PF, CANON>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
 }
 
 // Whole inverse transform of values v already in registers in the layout of

@@ -52,24 +52,37 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   const PrimeK pk = jb.primes[i];
   const A ar(pk);
   const uint32_t kind = tk.kind & PT_KIND_MASK;
+  // The batch's own transformed operands (inputs and plaintexts) stay in the
+  // policy's format: with fp64, doubles reduced to |v| <= 0.51 q (MacWsF64),
+  // so the multiply-accumulate reads them without conversions; with 64-bit
+  // integers, canonical residues.
+  constexpr bool kF64 = std::is_same<A, ArF64>::value;
   if (kind == PT_FWD_CT) {
     const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
     auto ld = [&](int k) { return ar.load(valid ? src[(uint32_t)k] : 0ull); };
-    auto st = [&](int k, uint64_t v) {
-      if (valid) dst[(uint32_t)k] = v;
+    auto st = [&](int k, V v) {
+      if constexpr (kF64) {
+        if (valid) dst[(uint32_t)k] = __builtin_bit_cast(uint64_t, ar.reduce(v));
+      } else {
+        if (valid) dst[(uint32_t)k] = ar.store(v);
+      }
     };
-    ntt_forward<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+    ntt_forward<A, G, false, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
-    auto st = [&](int k, uint64_t v) {
-      if (valid) dst[(uint32_t)k] = v;
+    auto st = [&](int k, V v) {
+      if constexpr (kF64) {
+        if (valid) dst[(uint32_t)k] = __builtin_bit_cast(uint64_t, ar.reduce(v));
+      } else {
+        if (valid) dst[(uint32_t)k] = ar.store(v);
+      }
     };
     if (jb.pkind == PK_POLY) {
       const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
       auto ld = [&](int k) { return ar.load_signed(valid ? src[(uint32_t)k] : 0ll); };
-      ntt_forward<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+      ntt_forward<A, G, false, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
 #pragma unroll
@@ -81,7 +94,8 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
         scatter_weights<A, G>(ar, lds_g, tid_g, wp, pp, as_global((const int32_t *)jb.plain));
       }
       __syncthreads();
-      ntt_forward_tc<A, G, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, LdsAt<typename A::V>{lds_g}, st);
+      ntt_forward_tc<A, G, false, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g,
+                                         LdsAt<typename A::V>{lds_g}, st);
     }
   } else {   // PT_MAC_INV: output plane (o, comp, i)
     const uint32_t comp = (plane / L) & 1, o = plane / (2 * L);
@@ -98,24 +112,32 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     }
     const HE_GLOBAL int32_t *cti = as_global(jb.cti), *pti = as_global(jb.pti);
     const HE_GLOBAL uint64_t *ct_hat = as_global((const uint64_t *)jb.ct_hat), *pt_hat = as_global((const uint64_t *)jb.pt_hat);
-    MacAcc<A> acc[G::E];
-    auto operands = [&](int t) {
-      uint32_t pa, pb;
-      if (listed && t == t0) {
-        pa = tk.a0;
-        pb = tk.b0;
-      } else {
-        pa = ((uint32_t)cti[t] * 2 + comp) * L + i;
-        pb = (uint32_t)pti[t] * L + i;
-      }
-      const HE_GLOBAL uint64_t *a = ct_hat + (size_t)pa * G::N;
-      const HE_GLOBAL uint64_t *b = pt_hat + (size_t)pb * G::N;
-      return std::pair<const HE_GLOBAL uint64_t *, const HE_GLOBAL uint64_t *>(a, b);
+    auto planes = [&](int t) {
+      if (listed && t == t0) return std::pair<uint32_t, uint32_t>(tk.a0, tk.b0);
+      return std::pair<uint32_t, uint32_t>(((uint32_t)cti[t] * 2 + comp) * L + i, (uint32_t)pti[t] * L + i);
     };
-    mac_terms<A, G::E>(ar, pk, acc, t0, t1, operands, [&](int e) { return slot_index<G, G::NPASS - 1>(tid_g, e); });
+    auto ix = [&](int e) { return slot_index<G, G::NPASS - 1>(tid_g, e); };
     V v[G::E];
+    if constexpr (kF64) {
+      auto operands = [&](int t) {
+        const auto [pa, pb] = planes(t);
+        return std::pair<const HE_GLOBAL uint64_t *, const HE_GLOBAL uint64_t *>(ct_hat + (size_t)pa * G::N,
+                                                                                 pt_hat + (size_t)pb * G::N);
+      };
+      // the inputs are the batch's own doubles unless the caller transformed them
+      if (jb.ct_f64) mac_terms_ws<false, G::E>(ar, v, t0, t1, operands, ix);
+      else mac_terms_ws<true, G::E>(ar, v, t0, t1, operands, ix);
+    } else {
+      MacAcc<A> acc[G::E];
+      auto operands = [&](int t) {
+        const auto [pa, pb] = planes(t);
+        return std::pair<const HE_GLOBAL uint64_t *, const HE_GLOBAL uint64_t *>(ct_hat + (size_t)pa * G::N,
+                                                                                 pt_hat + (size_t)pb * G::N);
+      };
+      mac_terms<A, G::E>(ar, pk, acc, t0, t1, operands, ix);
 #pragma unroll
-    for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
+      for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
+    }
     // (the first pass's twiddles are loaded here, not with the operands: held
     // across the products they would push the kernel past its register budget)
     const auto twi = PTw<A>::inv(jb) + (size_t)i * G::N;
@@ -123,6 +145,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     first.load(twi, tid_g);
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_out) + (size_t)plane * G::N;
     const uint64_t q = pk.q;
+    constexpr int kMacOut = kF64 ? MacWsF64::kOutBoundX100 : MacAcc<A>::kOutBoundX100;
     // the accumulate choice is uniform over the task: one inverse transform per
     // store kind keeps the per-coefficient stores free of branches
     if (jb.accumulate) {
@@ -132,13 +155,13 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
           dst[(uint32_t)k] = s >= q ? s - q : s;
         }
       };
-      ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100, false>(ar, twi, tid_g, lds_g, first, v, st);
+      ntt_inverse_regs<A, G, kMacOut, false>(ar, twi, tid_g, lds_g, first, v, st);
     } else {
       // streaming stores: output planes are not read again by this launch
       auto st = [&](int k, uint64_t x) {
         if (valid) __builtin_nontemporal_store(x, &dst[(uint32_t)k]);
       };
-      ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100, false>(ar, twi, tid_g, lds_g, first, v, st);
+      ntt_inverse_regs<A, G, kMacOut, false>(ar, twi, tid_g, lds_g, first, v, st);
     }
   }
 }

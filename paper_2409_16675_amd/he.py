@@ -26,6 +26,7 @@ HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0
 HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC, HE_KIND_DX = 0, 1, 2, 3
 HE_PREPARE_PPMUL, HE_PREPARE_CCMUL = 0x1, 0x2
 HE_NOALLOC_SCRATCH_MB = 64
+F64_MAX_BITS = 48          # HE_ARITH_F64 needs every prime below 2^48
 
 c_void_p, c_u32, c_u64, c_i32, c_size = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t
 u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -149,7 +150,7 @@ def lib():
 
 
 # ------------------------------------------------------------------ contexts
-def he_ctx_create(N, L, prime_bits=50, t=65537, q=None, arith=HE_ARITH_AUTO, device=0):
+def he_ctx_create(N, L, prime_bits=48, t=65537, q=None, arith=HE_ARITH_AUTO, device=0):
     p = he_params()
     p.N, p.L, p.prime_bits, p.arith, p.t, p.device = N, L, prime_bits, arith, t, device
     qa = None
@@ -554,7 +555,7 @@ def workspace(nbytes, device="cuda"):
 class Context:
     """Owns an he_ctx handle."""
 
-    def __init__(self, N, L, prime_bits=50, t=65537, q=None, arith=HE_ARITH_AUTO, device=0):
+    def __init__(self, N, L, prime_bits=48, t=65537, q=None, arith=HE_ARITH_AUTO, device=0):
         self.h = he_ctx_create(N, L, prime_bits, t, q, arith, device)
         self.N, self.L, self.t, self.arith = he_ctx_info(self.h)
         self.q, self.psi = he_ctx_moduli(self.h, self.L)

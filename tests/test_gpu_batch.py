@@ -229,3 +229,36 @@ def test_timed_out_wait_is_reported_after_a_later_run(gpu_lib, ctxs):
     he.he_batch_run(b)
     he.he_batch_sync(b)
     he.he_batch_destroy(b)
+
+
+@pytest.mark.gpu
+def test_batched_weight_gradient_full_size(gpu_lib, ctxs):
+    # the weight-gradient layer (batch 32, 16 -> 16 channels, 16x16 maps, 3x3
+    # kernel; CryptoTrain-P terms, 64 products per output, so the accumulators
+    # fold mid-sum) inside a persistent launch next to a conv job, twice
+    he = gpu_lib
+    N, L, B, C, M, H, h, P = 8192, 3, 32, 16, 16, 16, 3, 1
+    ctx = ctxs[(N, L)]
+    plan = he.Plan(ctx, he.HE_KIND_DW, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    cb = plan.info["cb"]
+    ct = synth.uniform_residues(synth.rng(3, synth.STREAM_CT, 9), (B * (cb + M), 2), ctx.q, N)
+    ptv = synth.uniform_mod_t(synth.rng(3, synth.STREAM_MASK, 9), (B * (M + cb), N))
+    row, cti, pti = packing.dw_terms(B, M, cb)
+    assert max(np.diff(row)) == 2 * B
+    expect = core.csr_cpmul(ct, core.lift(ptv, ctx.q), row, cti, pti, ctx.q, ctx.psi, method=2)
+    d_ct, d_pt = he.to_device_u64(ct), torch.from_numpy(ptv).cuda()
+    out = he.empty_u64((plan.info["n_ct_out"], 2, L, N))
+    conv = make_job(he, ctxs, 0, 1, 460)
+    b = he.he_batch_create(0)
+    he.he_batch_add(b, ctx.h, plan.h, d_ct, d_pt, out, he.HE_PLAIN_POLY)
+    he.he_batch_add(b, conv["ctx"].h, conv["plan"].h, conv["d_ct"], conv["d_w"], conv["out"], 0)
+    he.he_batch_build(b)
+    print("case batched dW full size", flush=True)
+    for rep in range(2):
+        out.view(torch.int64).zero_()
+        torch.cuda.synchronize()
+        he.he_batch_run(b)
+        he.he_batch_sync(b)
+        assert_equal_u64(he.to_numpy_u64(out), expect, "batched dW rep %d" % rep)
+        assert_equal_u64(he.to_numpy_u64(conv["out"]), oracle_out(conv), "conv beside dW rep %d" % rep)
+    he.he_batch_destroy(b)

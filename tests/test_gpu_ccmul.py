@@ -2,7 +2,7 @@
 (Section 3.2, the CCMul of the preprocessing phase) against the oracle, bit for
 bit, and through decryption: pairwise products with coefficients on the
 centring boundary, accumulated products over term lists, both arithmetic paths
-(fp64 below 2^50 and 64-bit integers for 60-bit primes), the conv layer's mask
+(fp64 below 2^48 and 64-bit integers for 60-bit primes), the conv layer's mask
 products at the benchmark ring, and the error paths."""
 import numpy as np
 import pytest
@@ -56,7 +56,7 @@ def _run(he, ctx, a, b, row, ai, bi, n_out, rlk_hat, flags=0):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(1024, 2, 50), (1024, 3, 50), (2048, 2, 60), (4096, 4, 50), (1024, 7, 50),
+@pytest.mark.parametrize("N,L,bits", [(1024, 2, 48), (1024, 3, 48), (2048, 2, 60), (4096, 4, 48), (1024, 7, 48),
                                       (1024, 1, 62)])
 def test_pairwise_products_match_oracle(gpu_lib, N, L, bits):
     he = gpu_lib
@@ -73,7 +73,7 @@ def test_pairwise_products_match_oracle(gpu_lib, N, L, bits):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(2048, 3, 50), (1024, 2, 60)])
+@pytest.mark.parametrize("N,L,bits", [(2048, 3, 48), (1024, 2, 60)])
 def test_accumulated_products_match_oracle_and_decrypt(gpu_lib, N, L, bits):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)
@@ -136,7 +136,7 @@ def test_conv_mask_products_at_the_benchmark_ring(gpu_lib):
     # N = 8192, L = 3): 256 outputs of one product each over the plan's term
     # lists; sampled outputs against the oracle, one through decryption
     he = gpu_lib
-    ctx = he.Context(8192, 3, prime_bits=50)
+    ctx = he.Context(8192, 3, prime_bits=48)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=16, C=3, M=16, H=32, W=32, h=3, P=1)
     row, cti, pti = he.he_plan_terms(plan.h)
     g, s, rlk = _keys(ctx, 84)
@@ -176,7 +176,7 @@ def test_ccmul_errors(gpu_lib):
     with pytest.raises(he.HeError) as ei:                  # too many products for one output
         _run(he, ctx, a, a, [0, 65537], big, big, 1, rlk_hat)
     assert ei.value.status == he.HE_EUNSUPPORTED
-    # eight 50-bit primes would need nine auxiliary ones: refused
+    # eight 48-bit primes would need nine auxiliary ones: refused
     ctx8 = he.Context(1024, 8)
     with pytest.raises(he.HeError) as ei:
         he.he_ctx_prepare(ctx8.h, he.HE_PREPARE_CCMUL, 1, 1)

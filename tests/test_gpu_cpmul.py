@@ -20,7 +20,7 @@ def c1_inputs(ctx, K=8):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("bits,arith", [(50, 1), (50, 2), (54, 2)])
+@pytest.mark.parametrize("bits,arith", [(48, 1), (48, 2), (50, 2), (54, 2)])
 def test_cpmul_acc_plain_workload_schoolbook(gpu_lib, bits, arith):
     he = gpu_lib
     ctx = he.Context(2048, 2, prime_bits=bits, arith=arith)
@@ -32,7 +32,7 @@ def test_cpmul_acc_plain_workload_schoolbook(gpu_lib, bits, arith):
     ws = he.workspace(he.he_cpmul_acc_ws(ctx.h, K))
     acc = he.empty_u64((2, 2, 2048))
     dct, dpt = he.to_device_u64(ct), he.to_device_u64(pt)
-    for arith2, loge in he.compiled_schedules(2048, f64_ok=bits <= 50):
+    for arith2, loge in he.compiled_schedules(2048, f64_ok=bits <= he.F64_MAX_BITS):
         print("case cpmul bits=%d arith=%d loge=%d" % (bits, arith2, loge), flush=True)
         for op in (he.HE_OP_FWD, he.HE_OP_INV, he.HE_OP_MAC):
             he.he_ctx_set_schedule(ctx.h, op, arith2, loge)
@@ -100,7 +100,7 @@ def test_cpmul_validate_rejects_out_of_range(gpu_lib):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(2048, 2, 50), (8192, 3, 50), (4096, 3, 60), (1024, 8, 50), (1024, 2, 62)])
+@pytest.mark.parametrize("N,L,bits", [(2048, 2, 48), (8192, 3, 48), (2048, 2, 50), (4096, 3, 60), (1024, 8, 48), (1024, 2, 62)])
 def test_encrypt_decrypt_match_oracle(gpu_lib, N, L, bits):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)

@@ -12,8 +12,8 @@ from oracle import core
 from paper_2409_16675_amd import synth
 from tests.helpers import assert_equal_u64
 
-RINGS = [(1024, 2, 50), (2048, 2, 50), (2048, 2, 54), (4096, 2, 50), (8192, 3, 50), (8192, 3, 60), (16384, 4, 50),
-         (1024, 8, 50), (2048, 2, 62)]          # the most primes, the widest primes
+RINGS = [(1024, 2, 48), (2048, 2, 48), (2048, 2, 54), (4096, 2, 50), (8192, 3, 48), (8192, 3, 60), (16384, 4, 48),
+         (1024, 8, 48), (2048, 2, 62)]          # the most primes, the widest primes (50 and 54 bits: integer path)
 
 
 @pytest.mark.gpu
@@ -23,7 +23,7 @@ def test_ctx_constants_match_oracle(gpu_lib, N, L, bits):
     ctx = he.Context(N, L, prime_bits=bits)
     q, psi = core.params(N, L, bits)
     assert ctx.q == q and ctx.psi == psi
-    assert ctx.arith == (he.HE_ARITH_F64 if bits <= 50 else he.HE_ARITH_U64)
+    assert ctx.arith == (he.HE_ARITH_F64 if bits <= he.F64_MAX_BITS else he.HE_ARITH_U64)
 
 
 @pytest.mark.gpu
@@ -35,7 +35,7 @@ def test_ntt_every_schedule_matches_oracle(gpu_lib, N, L, bits):
     n_polys = 3
     x = synth.uniform_residues(g, (n_polys,), ctx.q, N)
     expect = core.ntt_planes(x, ctx.q, ctx.psi)
-    for arith, loge in he.compiled_schedules(N, f64_ok=bits <= 50):
+    for arith, loge in he.compiled_schedules(N, f64_ok=bits <= he.F64_MAX_BITS):
         print("case N=%d L=%d bits=%d arith=%d loge=%d" % (N, L, bits, arith, loge), flush=True)
         he.he_ctx_set_schedule(ctx.h, he.HE_OP_FWD, arith, loge)
         he.he_ctx_set_schedule(ctx.h, he.HE_OP_INV, arith, loge)
@@ -49,7 +49,7 @@ def test_ntt_every_schedule_matches_oracle(gpu_lib, N, L, bits):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(8192, 3, 50), (4096, 2, 60), (16384, 4, 50), (1024, 8, 50), (2048, 2, 62)])
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 48), (4096, 2, 60), (16384, 4, 48), (1024, 8, 48), (2048, 2, 62)])
 def test_ntt_edge_values(gpu_lib, N, L, bits):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)
@@ -62,7 +62,7 @@ def test_ntt_edge_values(gpu_lib, N, L, bits):
     one_hot[:, N - 1] = qs[:, 0] - np.uint64(1)
     x = np.stack([zeros, top, alt, one_hot])
     expect = core.ntt_planes(x, ctx.q, ctx.psi)
-    for arith, loge in he.compiled_schedules(N, f64_ok=bits <= 50):
+    for arith, loge in he.compiled_schedules(N, f64_ok=bits <= he.F64_MAX_BITS):
         print("case edge N=%d arith=%d loge=%d" % (N, arith, loge), flush=True)
         he.he_ctx_set_schedule(ctx.h, he.HE_OP_FWD, arith, loge)
         he.he_ctx_set_schedule(ctx.h, he.HE_OP_INV, arith, loge)
@@ -109,14 +109,14 @@ def test_ntt_large_batch_sampled_against_definition(gpu_lib):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("N,L,bits", [(8192, 3, 50), (4096, 2, 60)])
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 48), (4096, 2, 60)])
 def test_autotune_candidates_are_all_exact_and_chosen_one_is_installed(gpu_lib, N, L, bits, tmp_path):
     he = gpu_lib
     ctx = he.Context(N, L, prime_bits=bits)
     cache = str(tmp_path / "tune.jsonl")
     rep = he.he_autotune(ctx.h, 64, cache)
     assert rep and all(r["exact"] for r in rep)
-    n_sched = len(he.compiled_schedules(N, f64_ok=bits <= 50))
+    n_sched = len(he.compiled_schedules(N, f64_ok=bits <= he.F64_MAX_BITS))
     assert len(rep) == 3 * n_sched
     chosen = [he.he_ctx_get_schedule(ctx.h, op) for op in (he.HE_OP_FWD, he.HE_OP_INV, he.HE_OP_MAC)]
     # the installed schedule: among the exact candidates within 5% of the fastest,

@@ -59,7 +59,7 @@ def test_ppmul_at_the_conv_workload_size(gpu_lib):
     # N = 8192, batch 16 x 3 -> 16 channels: 256 outputs, sampled coefficients
     # against the oracle's single-coefficient ring product mod t
     he = gpu_lib
-    ctx = he.Context(8192, 3, prime_bits=50)
+    ctx = he.Context(8192, 3, prime_bits=48)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=16, C=3, M=16, H=32, W=32, h=3, P=1)
     g = synth.rng(51, synth.STREAM_PT)
     a = g.integers(0, T, size=(16, 8192), dtype=np.uint64)

@@ -38,7 +38,7 @@ def _layer(he, ctx, plan, flags=0):
 @pytest.mark.parametrize("N,L,B,C,M,H,h,P", [(1024, 2, 2, 3, 2, 6, 3, 1), (8192, 3, 16, 3, 16, 32, 3, 1)])
 def test_seeded_layer_equals_full_ciphertext_layer(gpu_lib, N, L, B, C, M, H, h, P):
     he = gpu_lib
-    ctx = he.Context(N, L, prime_bits=50)
+    ctx = he.Context(N, L, prime_bits=48)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
     info = plan.info
     seed = (77, 2 ** 63 + 5)

@@ -1,4 +1,4 @@
-"""GPU parity with 60-bit primes: every kernel that the 50-bit default contexts
+"""GPU parity with 60-bit primes: every kernel that the 48-bit default contexts
 never reach runs here through the 64-bit integer arithmetic (Shoup products,
 128-bit multiply-accumulate, signed lifts through a 64-bit remainder).
 
