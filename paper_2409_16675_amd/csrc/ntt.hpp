@@ -150,11 +150,22 @@ struct MinWaves {
   static constexpr int value = w < 1 ? 1 : (w > 8 ? 8 : w);
 };
 
-// Index of register slot (g, p) of thread tid in a pass starting at stage S0 with R stages.
+// Index of register slot (g, p) of thread tid in a pass starting at stage S0
+// with R stages.  The pass's R stage bits hold the register slot p; the other
+// index bits take, from the lowest up, the lane bits of tid (tid & 63), the
+// group bits g, then the wave bits (tid >> 6).  So the lanes of a wave cover
+// the lowest free index bits (coalesced accesses at both ends of a transform)
+// and the wave bits sit on the highest free bits: every pass but the first
+// leaves the top LOGE bits free (they are the first pass's stage bits), so
+// when the wave bits fit there they hold the same index bits in all those
+// passes, and the exchanges between them stay inside each wave (no barrier).
 template <int LOGN, int LOGT, int S0, int R>
 __host__ __device__ constexpr int pass_index(int tid, int g, int p) {
   constexpr int NLOW = LOGN - S0 - R;
-  const int f = (g << LOGT) | tid;
+  constexpr int LOGNG = (LOGN - LOGT) - R;   // log2 of the radix-2^R groups per thread
+  int f = 0;
+  if constexpr (LOGT > 6) f = (tid & 63) | (g << 6) | ((tid >> 6) << (6 + LOGNG));
+  else f = (g << LOGT) | tid;
   const int low = f & ((1 << NLOW) - 1);
   const int high = f >> NLOW;
   return (high << (LOGN - S0)) | (p << NLOW) | low;
@@ -355,36 +366,51 @@ __device__ __forceinline__ typename A::V reduce_gs_in(const A &ar, typename A::V
 // and 1 (N^-1 folded in).  A pass's twiddles are loaded while the previous pass
 // is still running (between its arithmetic and its stores), so their latency
 // overlaps the stores, the barrier and the data loads.
+// Bits of tid (below `limit`) that pass K places above its stage bits.
+template <class G, int K>
+constexpr int thread_bits_above(int limit) {
+  constexpr int S0 = G::s0(K), R = G::r(K), NLOW = G::LOGN - S0 - R;
+  int m = 0;
+  for (int b = 0; b < limit && b < G::LOGT; ++b)
+    m |= pass_index<G::LOGN, G::LOGT, S0, R>(1 << b, 0, 0) >> (NLOW + R);
+  return m;
+}
+
 template <class A, class G, int K, bool INV>
 struct PassTw {
   static constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R, NLOW = G::LOGN - S0 - R;
   typename A::Tw w[NG][(1 << R) - 1];
   typename A::Tw n0, n1;
+  // the index bits above the stage bits ("high") select a group's entries
+  static constexpr bool kPlaneUniform = thread_bits_above<G, K>(G::LOGT) == 0;
+  static constexpr bool kWaveUniform = thread_bits_above<G, K>(6) == 0;
   template <class TwP>
   __device__ __forceinline__ void load(TwP tw, int tid) {
     using Tw = typename A::Tw;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      if constexpr (NLOW >= G::LOGT) {
-        // the high index bits hold no thread bits (tid < 2^LOGT <= 2^NLOW):
-        // the same entries for the whole plane
-        const uint32_t high = (uint32_t)g >> (NLOW - G::LOGT);
+      const uint32_t high_g = (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(0, g, 0) >> (NLOW + R);
+      if constexpr (kPlaneUniform) {
+        // the high index bits hold no thread bits: the same entries for the whole plane
+        const uint32_t high = high_g;
 #pragma unroll
         for (int u = 0; u < R; ++u)
 #pragma unroll
           for (int j = 0; j < (1 << u); ++j)
             w[g][(1 << u) - 1 + j] = load_tw_uniform<Tw>(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
-      } else if constexpr (NLOW >= 6) {
-        // the thread bits left in the high index bits are those above the
-        // lane bits (tid >> 6): the same entries across each wave
-        const uint32_t high = __builtin_amdgcn_readfirstlane((uint32_t)((g << G::LOGT) | tid) >> NLOW);
+      } else if constexpr (kWaveUniform) {
+        // the thread bits in the high index bits are wave bits (tid >> 6):
+        // the same entries across each wave
+        const uint32_t high =
+            __builtin_amdgcn_readfirstlane((uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0) >> (NLOW + R)) |
+            high_g;
 #pragma unroll
         for (int u = 0; u < R; ++u)
 #pragma unroll
           for (int j = 0; j < (1 << u); ++j)
             w[g][(1 << u) - 1 + j] = load_tw_uniform<Tw>(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
       } else {
-        const uint32_t high = (uint32_t)((g << G::LOGT) | tid) >> NLOW;
+        const uint32_t high = (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, 0) >> (NLOW + R);
 #pragma unroll
         for (int u = 0; u < R; ++u)
 #pragma unroll
@@ -517,6 +543,30 @@ struct LdsPut {
   __device__ __forceinline__ void operator()(int t, int c, V v) const { lds[lpad(t) + lpad_c(c)] = v; }
 };
 
+// Index bits that hold the wave bits of tid in pass K (none when a plane
+// fits in one wave).
+template <class G, int K>
+constexpr int wave_bits_at() {
+  int m = 0;
+  for (int b = 6; b < G::LOGT; ++b) m |= pass_index<G::LOGN, G::LOGT, G::s0(K), G::r(K)>(1 << b, 0, 0);
+  return m;
+}
+
+// Between pass KA's LDS stores and pass KB's LDS loads.  When the wave bits sit
+// on the same index bits in both passes, each wave reads back only slots it
+// wrote itself: a wave's LDS requests are served in order, so waiting for its
+// own stores to complete (lgkmcnt 0) suffices and the other waves run on.
+// Otherwise the whole workgroup meets at a barrier.
+template <class G, int KA, int KB>
+__device__ __forceinline__ void xchg_sync() {
+  if constexpr (wave_bits_at<G, KA>() == wave_bits_at<G, KB>()) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Forward passes K..NPASS-2, LDS to LDS; `cur` holds pass K's twiddles and
 // `last` receives pass NPASS-1's (the last pass is run by the caller, to the
 // destination).  PF: load the next pass's twiddles before this pass's stores
@@ -524,7 +574,7 @@ struct LdsPut {
 template <class A, class G, int K, bool PF, class TwP>
 __device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds,
                                                PassTw<A, G, K, false> &cur, PassTw<A, G, G::NPASS - 1, false> &last) {
-  __syncthreads();
+  xchg_sync<G, K - 1, K>();
   if constexpr (!PF) cur.load(tw, tid);
   if constexpr (K + 2 < G::NPASS) {
     PassTw<A, G, K + 1, false> nxt;
@@ -544,7 +594,7 @@ __device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typ
 template <class A, class G, int K, int B0X100, bool PF, class TwP>
 __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds,
                                                PassTw<A, G, K, true> &cur, PassTw<A, G, 0, true> &last) {
-  __syncthreads();
+  xchg_sync<G, K + 1, K>();
   if constexpr (!PF) cur.load(tw, tid);
   if constexpr (K > 1) {
     PassTw<A, G, K - 1, true> nxt;
@@ -588,7 +638,7 @@ __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typ
       if constexpr (PF) last.load(tw, tid);
     });
   }
-  __syncthreads();
+  xchg_sync<G, G::NPASS - 2, G::NPASS - 1>();
   if constexpr (!PF) last.load(tw, tid);
   auto out = [&](int i, V v) {
     if constexpr (CANON) st(i, ar.store(v));
@@ -634,7 +684,7 @@ __device__ __forceinline__ void ntt_inverse_regs(const A &ar, TwP tw, int tid, t
       if constexpr (PF) last.load(tw, tid);
     });
   }
-  __syncthreads();
+  xchg_sync<G, 1, 0>();
   if constexpr (!PF) last.load(tw, tid);
   auto st_out = [&](int t, int c, V x) { st(t + c, ar.store(x)); };
   inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
