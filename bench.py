@@ -79,18 +79,22 @@ def parse():
                     help="layer jobs (steps) the batched path runs per persistent launch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the weight-gradient, uneven-mix and 60-bit legs")
+    ap.add_argument("--preheat-ms", type=float, default=150.0,
+                    help="untimed launches before a timed region continue until the GPU has run this long")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for hardware byte counters)")
     ap.add_argument("--cpu-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
-def workload(he, synth, torch, n_layers=1):
+def workload(he, synth, torch, n_layers=1, bits=48):
     """The conv layer, `n_layers` independent instances of it (input batch and
     weights drawn from their own seeded streams), inputs encrypted on the device."""
     N, L, B, C, M, H, W, h, P = 8192, 3, 16, 3, 16, 32, 32, 3, 1
     import numpy as np
-    ctx = he.Context(N, L, prime_bits=48)
+    ctx = he.Context(N, L, prime_bits=bits)
     plan = he.Plan(ctx, he.HE_KIND_CONV, B=B, C=C, M=M, H=H, W=W, h=h, P=P)
     info = plan.info
     s = synth.ternary(synth.rng(2, synth.STREAM_SK), N)
@@ -113,12 +117,14 @@ def workload(he, synth, torch, n_layers=1):
     return dict(ctx=ctx, plan=plan, info=info, ct_in=layers[0]["ct_in"], w=layers[0]["w"], x=layers[0]["x"],
                 wh=layers[0]["wh"], layers=layers, N=N, L=L,
                 config=dict(workload="conv2d forward, batch 16 x 3x32x32 -> 16 channels, 3x3 kernel, stride 1, pad 1; "
-                                     "N=8192, 3 primes of 48 bits, t=65537; 256 CPMul-accumulates per step",
+                                     "N=8192, 3 primes of %d bits, t=65537; 256 CPMul-accumulates per step" % bits,
                             batch=B, in_channels=C, out_channels=M, map=[H, W], kernel=h, pad=P, N=N, L=L,
                             cpmul_per_step=info["n_terms"]))
 
 
-def time_path(he, torch, wl, flags, steps, warmup, profile=False):
+def time_path(he, torch, wl, flags, steps, warmup, profile=False, preheat_ms=0.0):
+    """The per-layer path (fused kernels, or with HE_UNFUSED separate ones),
+    one layer per step; untimed steps first as for the batched path."""
     ctx, plan = wl["ctx"], wl["plan"]
     out = he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"]))
     ws = he.workspace(plan.workspace_size(flags))
@@ -127,8 +133,12 @@ def time_path(he, torch, wl, flags, steps, warmup, profile=False):
     def step():
         he.he_corr_conv2d(ctx.h, plan.h, wl["ct_in"], wl["w"], out, flags, ws, ws.numel(), stream)
 
-    for _ in range(warmup):
+    t0, n = time.perf_counter(), 0
+    while n < warmup or (time.perf_counter() - t0) * 1e3 < preheat_ms:
         step()
+        n += 1
+        if n % 16 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     if profile:
         he.he_ctx_profile(ctx.h, True)
@@ -144,11 +154,52 @@ def time_path(he, torch, wl, flags, steps, warmup, profile=False):
     return (t1 - t0) / steps, stats, out
 
 
-def time_batched(he, torch, wl, steps, warmup, per_launch):
-    """The persistent fused kernel, replayed from a HIP graph, `per_launch` layer
-    jobs (steps) per launch; exactly `steps` steps are timed (a last launch with
-    fewer jobs takes the remainder).  Returns seconds per step, the persistent
-    kernel's average duration per full launch, job 0's output, batch info."""
+def launch_sizes(steps, per_launch):
+    """The fewest launches of at most `per_launch` jobs covering `steps` steps,
+    their sizes differing by at most one (20 steps at 16: two launches of 10)."""
+    n = max(1, -(-steps // max(1, per_launch)))
+    base, extra = divmod(steps, n)
+    return [base + 1] * extra + [base] * (n - extra)
+
+
+def kernel_us(he, b, stream, launches):
+    """Average duration of the persistent kernel alone over `launches` direct
+    launches of batch `b` (built with HE_BATCH_PROFILE): HIP events the library
+    records on the launch stream around the kernel, read at most 64 runs apart."""
+    he.he_batch_run(b, stream)                 # first launch untimed
+    he.he_batch_sync(b, stream)
+    k0 = he.he_batch_get_info(b)
+    left = launches
+    while left > 0:
+        c = min(64, left)
+        for _ in range(c):
+            he.he_batch_run(b, stream)
+        he.he_batch_sync(b, stream)
+        left -= c
+    k1 = he.he_batch_get_info(b)
+    return (k1["kernel_ms"] - k0["kernel_ms"]) / (k1["kernel_launches"] - k0["kernel_launches"]) * 1e3
+
+
+def preheat(he, b, stream, warmup, min_ms):
+    """`warmup` untimed launches, then more until the GPU has run the batch for
+    at least `min_ms` (its clocks settle over the first tens of milliseconds of
+    sustained load).  Returns the number of launches."""
+    t0, n = time.perf_counter(), 0
+    while n < warmup or (time.perf_counter() - t0) * 1e3 < min_ms:
+        he.he_batch_run(b, stream)
+        n += 1
+        if n % 16 == 0:
+            he.he_batch_sync(b, stream)
+    he.he_batch_sync(b, stream)
+    return n
+
+
+def time_batched(he, torch, wl, steps, warmup, per_launch, preheat_ms):
+    """The persistent fused kernel, replayed from a HIP graph, over exactly
+    `steps` layer jobs (steps) split into the fewest launches of at most
+    `per_launch` jobs, sizes within one of each other.  Returns seconds per
+    step, the kernel's average duration per full-size launch, the outputs of
+    the first launch's jobs, the batch and its info."""
     ctx, plan = wl["ctx"], wl["plan"]
     stream = torch.cuda.current_stream()
 
@@ -163,48 +214,179 @@ def time_batched(he, torch, wl, steps, warmup, per_launch):
         he.he_batch_build(b, flags)
         return b, outs
 
-    per_launch = max(1, min(per_launch, steps))
-    full, rest = steps // per_launch, steps % per_launch
-    b, outs = make(per_launch)
-    br = make(rest) if rest else None
-    prof, _ = make(per_launch, he.HE_BATCH_PROFILE)
-    for _ in range(warmup):
-        he.he_batch_run(b, stream)
-    he.he_batch_sync(b, stream)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(full)]
+    sizes = launch_sizes(steps, per_launch)
+    b, outs = make(sizes[0])
+    small = make(sizes[-1])[0] if sizes[-1] != sizes[0] else None
+    prof, _ = make(sizes[0], he.HE_BATCH_PROFILE)
+    n_pre = preheat(he, b, stream, warmup, preheat_ms)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sizes]
     t0 = time.perf_counter()
-    for a, z in ev:
+    for n, (a, z) in zip(sizes, ev):
         a.record(stream)
-        he.he_batch_run(b, stream)
+        he.he_batch_run(b if n == sizes[0] else small, stream)
         z.record(stream)
-    if br:
-        he.he_batch_run(br[0], stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     he.he_batch_sync(b, stream)
-    launch_ms = [a.elapsed_time(z) for a, z in ev]
+    launch_ms = [a.elapsed_time(z) for (a, z), n in zip(ev, sizes) if n == sizes[0]]
     info = he.he_batch_get_info(b)
-    if br:
-        he.he_batch_destroy(br[0])
-    # the persistent kernel alone: the same jobs launched directly, with HIP events
-    # recorded by the library on this stream right around the kernel (a graph
-    # replay also runs the control-word reset and the two cache-fence kernels)
-    he.he_batch_run(prof, stream)
-    he.he_batch_sync(prof, stream)
-    k0 = he.he_batch_get_info(prof)
-    n_prof = max(1, full)
-    while n_prof > 0:
-        # the library keeps the events of at most 64 profiled runs between syncs
-        c = min(64, n_prof)
-        for _ in range(c):
-            he.he_batch_run(prof, stream)
-        he.he_batch_sync(prof, stream)
-        n_prof -= c
-    k1 = he.he_batch_get_info(prof)
+    if small:
+        he.he_batch_sync(small, stream)
+        he.he_batch_destroy(small)
+    # the persistent kernel alone, on direct launches of the same jobs
+    kern = kernel_us(he, prof, stream, max(16, len(sizes)))
     he.he_batch_destroy(prof)
-    kern_ms = (k1["kernel_ms"] - k0["kernel_ms"]) / (k1["kernel_launches"] - k0["kernel_launches"])
-    info["graph_launch_ms"] = sum(launch_ms) / len(launch_ms) if launch_ms else float("nan")
-    return (t1 - t0) / steps, kern_ms, outs, b, info
+    info["graph_launch_ms"] = sum(launch_ms) / len(launch_ms)
+    info["launch_sizes"] = sizes
+    info["preheat_launches"] = n_pre
+    return (t1 - t0) / steps, kern / 1e3, outs, b, info
+
+
+def alg_work(specs):
+    """Algorithmic VALU operations and HBM bytes of a set of layer jobs run
+    once: forward transforms of inputs and plaintexts, the multiply-accumulate
+    terms and the inverse transforms of outputs (8 per butterfly, 8 per term
+    and coefficient, 6 per folded N^-1 product), and bytes of the inputs,
+    plaintexts and outputs read or written once.  specs: dicts with N, L, the
+    plan info, whether inputs come transformed, and the plaintext bytes."""
+    ops = bytes_ = 0
+    for sp in specs:
+        N, L, inf = sp["N"], sp["L"], sp["info"]
+        bfly = (N // 2) * (N.bit_length() - 1)
+        fwd = inf["n_pt"] * L + (0 if sp.get("in_ntt") else inf["n_ct_in"] * 2 * L)
+        inv = inf["n_ct_out"] * 2 * L
+        ops += fwd * bfly * OPS_BFLY + inv * (bfly * OPS_BFLY + (N // 2) * OPS_MODMUL) \
+            + inf["n_terms"] * 2 * L * N * OPS_MAC_TERM
+        bytes_ += 8 * N * (inf["n_ct_in"] * 2 * L + inf["n_ct_out"] * 2 * L) + sp["plain_bytes"]
+    return ops, bytes_
+
+
+def roofline_of(ops, bytes_, kern_s, what):
+    alu = ops / kern_s / 1e12
+    hbm = bytes_ / kern_s / 1e9
+    return {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_VALU_TOPS, 3), "unit": "T VALU-op/s",
+            "frac": round(alu / PEAK_VALU_TOPS, 4), "kernel": what, "kernel_avg_us": round(kern_s * 1e6, 2),
+            "ops_per_launch": int(ops), "alg_bytes_per_launch": int(bytes_), "hbm_achieved_GBs": round(hbm, 1),
+            "hbm_frac": round(hbm / PEAK_HBM_GBS, 4)}
+
+
+def time_job_set(he, torch, jobs, reps, warmup, preheat_ms, per_layer=True):
+    """A set of layer jobs (ctx, plan, ct_in, plain, out, flags, spec): one
+    persistent launch per step, replayed from a HIP graph (`reps` steps timed
+    after a pre-heat), the kernel alone on direct launches, and -- with
+    per_layer -- the same jobs one after another through the fused and the
+    plain (unfused) per-layer kernels.  Outputs of all three paths are
+    compared byte for byte."""
+    stream = torch.cuda.current_stream()
+
+    def make(flags):
+        b = he.he_batch_create(0)
+        for ctx, plan, ct, pl, out, f, _ in jobs:
+            he.he_batch_add(b, ctx.h, plan.h, ct, pl, out, f)
+        he.he_batch_build(b, flags)
+        return b
+
+    b, prof = make(he.HE_BATCH_GRAPH), make(he.HE_BATCH_PROFILE)
+    n_pre = preheat(he, b, stream, warmup, preheat_ms)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        he.he_batch_run(b, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    he.he_batch_sync(b, stream)
+    info = he.he_batch_get_info(b)
+    kern = kernel_us(he, prof, stream, max(16, reps))
+    batched_out = [j[4].clone() for j in jobs]
+    he.he_batch_destroy(prof)
+    he.he_batch_destroy(b)
+    res = {"batched_ms_per_step": round(dt * 1e3, 4), "kernel_us": round(kern, 2), "jobs": len(jobs),
+           "cpmul_per_step": int(info["cpmul"]), "batched_cpmul_per_s": round(info["cpmul"] / dt, 1),
+           "fwd_planes": int(info["fwd_planes"]), "inv_planes": int(info["inv_planes"]), "preheat_launches": n_pre}
+    if per_layer:
+        wss = [he.workspace(plan.workspace_size(f | he.HE_UNFUSED)) for _, plan, _, _, _, f, _ in jobs]
+        same = True
+        for name, extra in (("fused", 0), ("plain", he.HE_UNFUSED)):
+            def step():
+                for (ctx, plan, ct, pl, out, f, _), ws in zip(jobs, wss):
+                    he.he_corr_conv2d(ctx.h, plan.h, ct, pl, out, f | extra, ws, ws.numel(), stream)
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            d = (time.perf_counter() - t0) / reps
+            res[name + "_ms_per_step"] = round(d * 1e3, 4)
+            res[name + "_cpmul_per_s"] = round(info["cpmul"] / d, 1)
+            same = same and all(torch.equal(j[4].view(torch.int64), o.view(torch.int64)) for j, o in zip(jobs, batched_out))
+        res["batched_equals_fused_equals_plain"] = bool(same)
+    ops, bytes_ = alg_work([j[6] for j in jobs])
+    res["roofline"] = roofline_of(ops, bytes_, kern * 1e-6, "k_persistent (%d jobs per launch)" % len(jobs))
+    return res
+
+
+def weight_gradient_leg(he, torch, synth, reps, warmup, preheat_ms):
+    """The weight-gradient workload: batch 32, 16 -> 16 channels, 16x16 maps,
+    3x3 kernel, pad 1, N = 8192, 3 primes; ciphertexts uniform mod q_i and
+    plaintext polynomials uniform mod t (the masked shares of Section 3.2),
+    CryptoTrain-P terms [X](dY - r) + [dY](X - r): 2048 CPMul into 32 outputs."""
+    import numpy as np
+    N, L, B, C, M, H, h, P = 8192, 3, 32, 16, 16, 16, 3, 1
+    ctx = he.Context(N, L)
+    plan = he.Plan(ctx, he.HE_KIND_DW, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    info = plan.info
+    ct = he.to_device_u64(synth.uniform_residues(synth.rng(3, synth.STREAM_CT), (info["n_ct_in"], 2), ctx.q, N))
+    pt = torch.from_numpy(synth.uniform_mod_t(synth.rng(3, synth.STREAM_MASK), (info["n_pt"], N))).cuda()
+    out = he.empty_u64((info["n_ct_out"], 2, L, N))
+    spec = dict(N=N, L=L, info=info, plain_bytes=info["n_pt"] * N * 8)
+    res = time_job_set(he, torch, [(ctx, plan, ct, pt, out, he.HE_PLAIN_POLY, spec)], reps, warmup, preheat_ms)
+    res["workload"] = ("conv2d weight gradient, batch 32, 16 -> 16 channels, 16x16 maps, 3x3 kernel, pad 1; "
+                       "N=8192, 3 primes of 48 bits; CryptoTrain-P terms, %d CPMul-accumulates" % info["n_terms"])
+    return res
+
+
+def mix_leg(he, torch, synth, reps, warmup, preheat_ms, n_jobs=64):
+    """The uneven mix: 64 jobs drawn over {conv 3->16 @32x32, 16->32 @16x16,
+    32->64 @8x8, FC 256->10, FC 1024->256} x {(4096, 2), (8192, 3), (16384, 4)},
+    batch 1, ciphertexts uniform mod q_i, int8 weights, all in one persistent
+    launch (the mixed-degree variant) replayed from a HIP graph."""
+    import numpy as np
+    ctxs = {(N, L): he.Context(N, L) for N, L in synth.MIX_RINGS}
+    jobs = []
+    for k, (lay, ring) in enumerate(synth.job_mix(n_jobs)):
+        N, L = synth.MIX_RINGS[ring]
+        ctx = ctxs[(N, L)]
+        spec = synth.MIX_LAYERS[lay]
+        gw = synth.rng(4, synth.STREAM_PT, k)
+        if spec[0] == "conv":
+            _, C, M, H, W, h, P = spec
+            plan = he.Plan(ctx, he.HE_KIND_CONV, B=1, C=C, M=M, H=H, W=W, h=h, P=P)
+            w = synth.int8_uniform(gw, (M, C, h, h))
+        else:
+            _, n_in, n_out = spec
+            plan = he.Plan(ctx, he.HE_KIND_FC, B=1, n_in=n_in, n_out=n_out)
+            w = synth.int8_uniform(gw, (n_out, n_in))
+        info = plan.info
+        ct = he.to_device_u64(synth.uniform_residues(synth.rng(4, synth.STREAM_CT, k), (info["n_ct_in"], 2), ctx.q, N))
+        out = he.empty_u64((info["n_ct_out"], 2, L, N))
+        jobs.append((ctx, plan, ct, torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda(), out, 0,
+                     dict(N=N, L=L, info=info, plain_bytes=w.size * 4)))
+    res = time_job_set(he, torch, jobs, reps, warmup, preheat_ms)
+    res["workload"] = "uneven mix of %d layer jobs over N = 4096 / 8192 / 16384 (2 / 3 / 4 primes of 48 bits)" % n_jobs
+    return res
+
+
+def wide_prime_leg(he, torch, synth, reps, warmup, preheat_ms, jobs_per_launch=16):
+    """The conv-forward workload with three 60-bit primes (64-bit integer
+    arithmetic throughout): `jobs_per_launch` instances in one persistent launch."""
+    wl = workload(he, synth, torch, n_layers=jobs_per_launch, bits=60)
+    jobs = [(wl["ctx"], wl["plan"], lay["ct_in"], lay["w"], he.empty_u64((wl["info"]["n_ct_out"], 2, wl["L"], wl["N"])),
+             0, dict(N=wl["N"], L=wl["L"], info=wl["info"], plain_bytes=lay["w"].numel() * 4)) for lay in wl["layers"]]
+    res = time_job_set(he, torch, jobs, reps, warmup, preheat_ms)
+    res["workload"] = wl["config"]["workload"]
+    res["arith"] = "u64" if wl["ctx"].arith == he.HE_ARITH_U64 else "f64"
+    return res
 
 
 def time_seeded(he, torch, wl, steps, warmup):
@@ -358,11 +540,17 @@ def roofline_persistent(wl, kern_ms, binfo):
             "graph_replay_avg_us": round(binfo["graph_launch_ms"] * 1e3, 2)}
 
 
-def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4, sweep=(20000.0, 100000.0)):
-    """Poisson arrivals (mean `rate` jobs/s) drawn from the uneven layer mix, sessions of 6
-    jobs whose transformed inputs stay resident, 64 GB admission cap; continuous batching
-    against the sequential per-layer server on the same trace; then the same at the
-    higher arrival rates of `sweep` (where the sequential server saturates)."""
+def serving(he, torch, synth, n_jobs=20000, rate=2000.0, copies=4, sweep=(20000.0, 100000.0), sweep_jobs=4000,
+            reuse_jobs=6000):
+    """Poisson arrivals (mean `rate` jobs/s) of jobs drawn from the uneven layer
+    mix, sessions of 6 jobs keeping their transformed inputs resident, 64 GB
+    admission cap, continuous batching against the sequential per-layer server
+    on the same trace; each server is warmed by a burst of jobs and then
+    measured on the trace (latency from each job's scheduled arrival to its
+    completion seen by the server).  Then the same at the higher arrival rates
+    of `sweep`, and a training-step trace whose sessions are three pairs of
+    jobs on the same input ciphertexts (the second of each pair with other
+    weights, HE_IN_RESIDENT), with and without reuse of the kept transforms."""
     import numpy as np
     ctxs = {(N, L): he.Context(N, L) for N, L in synth.MIX_RINGS}
     kinds = {}
@@ -372,58 +560,76 @@ def serving(he, torch, synth, n_jobs=2000, rate=2000.0, copies=4, sweep=(20000.0
             if spec[0] == "conv":
                 _, C, M, H, W, h, P = spec
                 plan = he.Plan(ctx, he.HE_KIND_CONV, B=1, C=C, M=M, H=H, W=W, h=h, P=P)
-                w = synth.int8_uniform(synth.rng(5, synth.STREAM_PT, li), (M, C, h, h))
+                ws = [synth.int8_uniform(synth.rng(5, synth.STREAM_PT, 10 * li + k), (M, C, h, h)) for k in range(2)]
             else:
                 _, n_in, n_out = spec
                 plan = he.Plan(ctx, he.HE_KIND_FC, B=1, n_in=n_in, n_out=n_out)
-                w = synth.int8_uniform(synth.rng(5, synth.STREAM_PT, li), (n_out, n_in))
+                ws = [synth.int8_uniform(synth.rng(5, synth.STREAM_PT, 10 * li + k), (n_out, n_in)) for k in range(2)]
             info = plan.info
             g = synth.rng(5, synth.STREAM_CT, 10 * li + ri)
             bufs = [(he.to_device_u64(synth.uniform_residues(g, (info["n_ct_in"], 2), ctx.q, N)),
-                     he.empty_u64((info["n_ct_out"], 2, L, N))) for _ in range(copies)]
-            kinds[(li, ri)] = dict(ctx=ctx, plan=plan, w=torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda(),
-                                   bufs=bufs, cpmul=info["n_terms"])
-    mix = synth.job_mix(n_jobs, workload=5)
-    jobs, ctx_list, cpmul = [], [], 0
+                     he.empty_u64((info["n_ct_out"], 2, L, N)), he.empty_u64((info["n_ct_out"], 2, L, N)))
+                    for _ in range(copies)]
+            kinds[(li, ri)] = dict(ctx=ctx, plan=plan, bufs=bufs, cpmul=info["n_terms"],
+                                   w=[torch.from_numpy(w.astype(np.int32).reshape(-1)).cuda() for w in ws])
+    mix = synth.job_mix(max(n_jobs, reuse_jobs, sweep_jobs), workload=5)
+    jobs, twins, ctx_list, cpmul = [], [], [], []
     for k, (li, ri) in enumerate(mix):
         kd = kinds[(li, ri)]
-        ct, out = kd["bufs"][k % copies]
-        jobs.append((kd["plan"].h, ct, kd["w"], out, 0))
+        ct, out, out2 = kd["bufs"][k % copies]
+        jobs.append((kd["plan"].h, ct, kd["w"][0], out, 0))
+        twins.append((kd["plan"].h, ct, kd["w"][1], out2, he.HE_IN_RESIDENT))
         ctx_list.append(kd["ctx"].h)
-        cpmul += kd["cpmul"]
-    sessions = np.arange(n_jobs, dtype=np.uint64) // 6 + 1
+        cpmul.append(kd["cpmul"])
 
-    def run(r):
-        arr = synth.poisson_arrivals(n_jobs, r)
+    def run(r, n, modes, job_list, ctx_l, cp_l, flags):
+        arr = synth.poisson_arrivals(n, r)
         arr = arr - arr[0]
+        sessions = np.arange(n, dtype=np.uint64) // 6 + 1
         out = {}
-        for name, mode in (("continuous", he.HE_SERVE_CONTINUOUS), ("sequential", he.HE_SERVE_SEQUENTIAL)):
+        for name, mode in modes:
             srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
                                       max_batch_jobs=64, session_jobs=6)
-            # warm the kernels and the arena with a short burst
-            he.he_server_replay(srv, ctx_list[:32], jobs[:32], np.zeros(32))
-            he.he_server_destroy(srv)
-            srv = he.he_server_create(mem_cap_bytes=64 << 30, mode=mode, arena_bytes=8 << 30, slots=2,
-                                      max_batch_jobs=64, session_jobs=6)
+            # warm the kernels, arena and tables of this server with a burst, then measure
+            he.he_server_replay(srv, ctx_list[:64], jobs[:64], np.zeros(64))
+            st0 = he.he_server_stats(srv)
             t0 = time.perf_counter()
-            lat = he.he_server_replay(srv, ctx_list, jobs, arr, sessions, he.HE_SERVE_KEEP_RESIDENT)
+            lat = he.he_server_replay(srv, ctx_l[:n], job_list[:n], arr, sessions, flags)
             wall = time.perf_counter() - t0
             st = he.he_server_stats(srv)
             he.he_server_destroy(srv)
+            span = float((arr + lat).max())
             out[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                          "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                          "mean_ms": round(float(lat.mean()) * 1e3, 3),
-                         "throughput_jobs_per_s": round(n_jobs / st["span_s"], 1),
-                         "cpmul_per_s": round(cpmul / st["span_s"], 1),
-                         "epochs": st["epochs"], "single_job_epochs": st["single_epochs"],
-                         "mean_jobs_per_epoch": round(st["mean_jobs_per_epoch"], 2),
+                         "throughput_jobs_per_s": round(n / span, 1),
+                         "cpmul_per_s": round(sum(cp_l[:n]) / span, 1),
+                         "epochs": st["epochs"] - st0["epochs"],
+                         "single_job_epochs": st["single_epochs"] - st0["single_epochs"],
+                         "fwd_planes": st["fwd_planes"] - st0["fwd_planes"],
+                         "resident_hits": st["resident_hits"] - st0["resident_hits"],
                          "peak_footprint_GB": round(st["peak_bytes"] / 2 ** 30, 3), "wall_s": round(wall, 3)}
+            e = out[name]["epochs"]
+            out[name]["mean_jobs_per_epoch"] = round(n / e, 2) if e else 0.0
         return out
 
+    both = (("continuous", he.HE_SERVE_CONTINUOUS), ("sequential", he.HE_SERVE_SEQUENTIAL))
     res = {"rate_jobs_per_s": rate, "jobs": n_jobs, "mix": "uneven 5-layer x 3-ring mix, batch 1",
-           "session_jobs": 6, "cap_GB": 64}
-    res.update(run(rate))
-    res["sweep"] = [dict(rate_jobs_per_s=r, **run(r)) for r in sweep]
+           "session_jobs": 6, "cap_GB": 64, "server": "warmed by a 64-job burst before each measured trace"}
+    res.update(run(rate, n_jobs, both, jobs, ctx_list, cpmul, he.HE_SERVE_KEEP_RESIDENT))
+    res["sweep"] = [dict(rate_jobs_per_s=r, jobs=sweep_jobs,
+                         **run(r, sweep_jobs, both, jobs, ctx_list, cpmul, he.HE_SERVE_KEEP_RESIDENT)) for r in sweep]
+    # training-step sessions: pairs of jobs on the same inputs
+    half = reuse_jobs // 2
+    step = [j for k in range(half) for j in (jobs[k], twins[k])]
+    step_ctx = [c for k in range(half) for c in (ctx_list[k], ctx_list[k])]
+    step_cp = [c for k in range(half) for c in (cpmul[k], cpmul[k])]
+    no_reuse = [(p, c, w, o, 0) for p, c, w, o, _ in step]
+    res["training_step"] = {
+        "what": "sessions of 6 = 3 pairs of jobs on the same input ciphertexts, the second with other weights",
+        "jobs": reuse_jobs, "rate_jobs_per_s": rate,
+        "with_reuse": run(rate, reuse_jobs, both[:1], step, step_ctx, step_cp, he.HE_SERVE_KEEP_RESIDENT)["continuous"],
+        "without_reuse": run(rate, reuse_jobs, both[:1], no_reuse, step_ctx, step_cp, 0)["continuous"]}
     return res
 
 
@@ -461,9 +667,12 @@ def main():
     tune = he.he_autotune(wl["ctx"].h, 512)      # set-up: picks the fastest bit-exact schedules
     chosen = {name: he.he_ctx_get_schedule(wl["ctx"].h, op) for name, op in
               (("fwd", he.HE_OP_FWD), ("inv", he.HE_OP_INV), ("mac", he.HE_OP_MAC))}
-    plain_dt, _, out_plain = time_path(he, torch, wl, he.HE_UNFUSED, max(5, args.steps // 2), args.warmup)
-    fused_dt, stats, out_fused = time_path(he, torch, wl, 0, max(5, args.steps // 2), args.warmup, profile=True)
-    dt, kern_ms, outs, batch, binfo = time_batched(he, torch, wl, args.steps, args.warmup, args.jobs_per_launch)
+    plain_dt, _, out_plain = time_path(he, torch, wl, he.HE_UNFUSED, max(5, args.steps // 2), args.warmup,
+                                       preheat_ms=args.preheat_ms)
+    fused_dt, stats, out_fused = time_path(he, torch, wl, 0, max(5, args.steps // 2), args.warmup, profile=True,
+                                           preheat_ms=args.preheat_ms)
+    dt, kern_ms, outs, batch, binfo = time_batched(he, torch, wl, args.steps, args.warmup, args.jobs_per_launch,
+                                                   args.preheat_ms)
     same = bool(torch.equal(outs[0].view(torch.int64), out_plain.view(torch.int64)) and
                 torch.equal(out_fused.view(torch.int64), out_plain.view(torch.int64)))
     # every other job of the launch against the fused per-layer path on its own layer
@@ -481,8 +690,11 @@ def main():
         "metric": METRIC, "value": round(n_cpmul / dt, 1), "unit": "CPMul-acc/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
-        "path": "batched (persistent fused kernel, graph replay, %d layer jobs per launch)" % args.jobs_per_launch,
-        "jobs_per_launch": args.jobs_per_launch,
+        "path": "batched (persistent fused kernel, graph replay, up to %d layer jobs per launch)" % args.jobs_per_launch,
+        "jobs_per_launch": args.jobs_per_launch, "launch_sizes": binfo["launch_sizes"],
+        "preheat": {"launches": binfo["preheat_launches"], "min_ms": args.preheat_ms,
+                    "what": "untimed launches of the batch before the timed region (at least --warmup, then until "
+                            "the GPU has run for min_ms)"},
         "kernel_src_sha": kernel_src_sha(),
         "plain_value": round(n_cpmul / plain_dt, 1), "plain_ms_per_step": round(plain_dt * 1e3, 4),
         "fused_value": round(n_cpmul / fused_dt, 1), "fused_ms_per_step": round(fused_dt * 1e3, 4),
@@ -515,6 +727,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         res["calib_copy_bytes"] = src.numel() * 8
+    if not args.no_legs:
+        reps = max(8, min(64, args.steps // 4))
+        res["weight_gradient"] = weight_gradient_leg(he, torch, synth, reps, args.warmup, args.preheat_ms)
+        res["uneven_mix"] = mix_leg(he, torch, synth, reps, args.warmup, args.preheat_ms)
+        res["wide_primes_60bit"] = wide_prime_leg(he, torch, synth, reps, args.warmup, args.preheat_ms,
+                                                  args.jobs_per_launch)
     if not args.no_serve:
         res["serving"] = serving(he, torch, synth)
     if not args.no_cpu:

@@ -152,6 +152,8 @@ he_status he_ntt_inv(he_ctx *ctx, uint64_t *planes, uint32_t n_polys, void *stre
 #define HE_PLAIN_POLY 0x10u    /* he_corr_conv2d: `plain` holds packed int64 polynomials */
 #define HE_FUSED 0x0u          /* one fused multiply-accumulate + inverse-transform kernel (default) */
 #define HE_UNFUSED 0x20u       /* separate transform, multiply-accumulate and inverse kernels */
+#define HE_IN_RESIDENT 0x40u   /* he_server_submit only: read the transform of ct_in kept by an earlier
+                                  HE_SERVE_KEEP_RESIDENT job of the same session (see the serving section) */
 
 /* CPMul + CCAdd (Section 2 "Motivation", Section 3.2):
  *   acc_c = sum_{k<K} ct[k]_c (x) pt[k]   (ring product per prime), c = 0, 1.
@@ -441,7 +443,23 @@ he_status he_batch_destroy(he_batch *b);
  * the next epoch on another stream and overlap on the device; SEQUENTIAL mode
  * serves one job at a time through the per-layer path (the plain baseline).
  * Latency is measured from arrival (submission, or the scheduled arrival in
- * he_server_replay) to completion observed by the server thread. */
+ * he_server_replay) to completion observed by the server thread.
+ *
+ * Residency (the layers of a training step reuse their inputs, Section 2
+ * "Neural Network Training"): the forward transform of a job's input
+ * ciphertexts depends only on the ciphertexts and the context.  A job
+ * submitted with HE_SERVE_KEEP_RESIDENT and a session keeps, after it
+ * finishes, its workspace block holding that transform (canonical residues).
+ * A later job of the same session whose he_job.flags has HE_IN_RESIDENT and
+ * whose ct_in is the same buffer (same context, at most as many ciphertexts)
+ * reads that transform instead of computing it; if none is kept (the
+ * producer has not finished, was evicted, or never kept), it transforms ct_in
+ * as usual.  Results are identical either way.  Kept blocks count towards the
+ * cap; they are freed when the session closes (after session_jobs jobs, or by
+ * he_server_close_session) and evicted, oldest first and only when no running
+ * job reads them, when the queue head does not fit while no epoch runs.
+ * A job with HE_VALIDATE is checked by itself before its epoch is built: a
+ * job with a coefficient outside [0, q_i) fails alone with HE_ERANGE. */
 #define HE_SERVE_CONTINUOUS 0
 #define HE_SERVE_SEQUENTIAL 1
 #define HE_SERVE_KEEP_RESIDENT 0x1u   /* he_server_submit flag: keep the job's transformed inputs until its session closes */
@@ -470,6 +488,12 @@ typedef struct {
   double span_s;              /* first arrival to last completion */
   uint64_t peak_bytes, in_use_bytes;
   uint64_t single_epochs;     /* continuous mode: epochs of one job, run by the per-layer kernels */
+  uint64_t resident_hits;     /* HE_IN_RESIDENT jobs that read a kept transform */
+  uint64_t resident_misses;   /* HE_IN_RESIDENT jobs that found none and transformed their inputs */
+  uint64_t evictions;         /* kept blocks freed to admit the queue head */
+  uint64_t fwd_planes;        /* plane forward transforms the served jobs ran */
+  uint64_t failed;            /* jobs that finished with an error status */
+  uint64_t resident_blocks;   /* kept blocks now on the device */
 } he_server_info;
 
 /* Start a server (device arena, stream slots and the server thread). */
@@ -479,10 +503,13 @@ he_status he_server_create(const he_server_params *params, he_server **out);
  * job's transformed inputs stay on the device until the session closes. */
 he_status he_server_submit(he_server *s, he_ctx *ctx, const he_job *job, uint64_t session, uint32_t flags,
                            uint64_t *ticket);
-/* Wait for a job (timeout_us < 0: no limit); returns the job's status or HE_ETIMEOUT. */
+/* Wait for a job (timeout_us < 0: no limit); returns the job's status (result->status
+ * too) or HE_ETIMEOUT if it has not finished. */
 he_status he_server_wait(he_server *s, uint64_t ticket, int64_t timeout_us, he_job_result *result);
 /* Wait until every queued job has finished. */
 he_status he_server_drain(he_server *s);
+/* Free the blocks a session keeps (a block a running job reads is freed when it finishes). */
+he_status he_server_close_session(he_server *s, uint64_t session);
 /* Submit n jobs at arrival_s[i] seconds after the call (busy-waiting on the host
  * clock), wait for all, and write each latency (from its scheduled arrival) to
  * latency_s[i] (host, may be NULL; -1 for a rejected job). */

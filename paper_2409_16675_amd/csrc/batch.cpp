@@ -59,18 +59,15 @@ namespace he {
 
 static inline size_t al256b(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// bytes of the transformed plaintexts of a job
-static size_t pt_hat_bytes(const JobRef &j) {
+// bytes of the transformed inputs of a job (none when already transformed)
+static size_t ct_hat_bytes(const JobRef &j) {
   const size_t plane = (size_t)j.ctx->L * j.ctx->N * 8;
-  return al256b((size_t)j.plan->info.n_pt * plane);
+  return (j.job.flags & HE_IN_NTT) ? 0 : al256b((size_t)j.plan->info.n_ct_in * 2 * plane);
 }
 
 size_t job_ws_bytes(const JobRef &j) {
-  const he_plan_info &in = j.plan->info;
   const size_t plane = (size_t)j.ctx->L * j.ctx->N * 8;
-  size_t b = pt_hat_bytes(j);
-  if (!(j.job.flags & HE_IN_NTT)) b += al256b((size_t)in.n_ct_in * 2 * plane);
-  return b;
+  return ct_hat_bytes(j) + al256b((size_t)j.plan->info.n_pt * plane);
 }
 
 static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
@@ -84,9 +81,9 @@ static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
   pj.tw_fwd = arith == HE_ARITH_F64 ? c.d_tw_f64_fwd : c.d_tw_u64_fwd;
   pj.tw_inv = arith == HE_ARITH_F64 ? c.d_tw_f64_inv : c.d_tw_u64_inv;
   pj.ct_in = bj.job.ct_in;
-  pj.pt_hat = (uint64_t *)ws;
-  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in) : (uint64_t *)(ws + pt_hat_bytes(bj));
-  pj.ct_f64 = (arith == HE_ARITH_F64 && !(f & HE_IN_NTT)) ? 1u : 0u;
+  pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in) : (uint64_t *)ws;
+  pj.pt_hat = (uint64_t *)(ws + ct_hat_bytes(bj));
+  pj.ct_f64 = (arith == HE_ARITH_F64 && !(f & HE_IN_NTT) && !bj.canon_ct) ? 1u : 0u;
   pj.plain = bj.job.plain;
   pj.ct_out = bj.job.ct_out;
   pj.row = p.d_row();

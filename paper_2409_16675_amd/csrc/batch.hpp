@@ -50,10 +50,12 @@ struct JobRef {
   Ctx *ctx;
   const Plan *plan;
   he_job job;
+  bool canon_ct = false;   // keep the transformed inputs as canonical residues (read again by later jobs)
 };
 
-// Device workspace a job needs inside a persistent launch (transformed inputs
-// unless already transformed, transformed plaintexts).
+// Device workspace a job needs inside a persistent launch: transformed inputs
+// (unless already transformed) first, at offset 0 as in the per-layer path's
+// workspace, then the transformed plaintexts.
 size_t job_ws_bytes(const JobRef &j);
 // Task table and device job descriptors for `jobs`, with job k's workspace at
 // ws[k].  Every pre task precedes every multiply-accumulate task.

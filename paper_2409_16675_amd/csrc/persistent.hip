@@ -61,9 +61,11 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
     auto ld = [&](int k) { return ar.load(valid ? src[(uint32_t)k] : 0ull); };
+    // (inputs kept for later jobs are stored as canonical residues: ct_f64 = 0)
+    const bool as_f64 = kF64 && jb.ct_f64;
     auto st = [&](int k, V v) {
       if constexpr (kF64) {
-        if (valid) dst[(uint32_t)k] = __builtin_bit_cast(uint64_t, ar.reduce(v));
+        if (valid) dst[(uint32_t)k] = as_f64 ? __builtin_bit_cast(uint64_t, ar.reduce(v)) : ar.store(v);
       } else {
         if (valid) dst[(uint32_t)k] = ar.store(v);
       }

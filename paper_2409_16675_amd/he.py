@@ -23,6 +23,7 @@ HE_OK = 0
 HE_EINVAL, HE_EUNSUPPORTED, HE_ENOMEM, HE_EDEVICE, HE_ERANGE, HE_EBUSY, HE_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 HE_ARITH_AUTO, HE_ARITH_F64, HE_ARITH_U64 = 0, 1, 2
 HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+HE_IN_RESIDENT = 0x40
 HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC, HE_KIND_DX = 0, 1, 2, 3
 HE_PREPARE_PPMUL, HE_PREPARE_CCMUL = 0x1, 0x2
 HE_NOALLOC_SCRATCH_MB = 64
@@ -100,6 +101,7 @@ _SIGS = {
     "he_server_submit": [c_void_p, c_void_p, c_void_p, c_u64, c_u32, ctypes.POINTER(c_u64)],
     "he_server_wait": [c_void_p, c_u64, ctypes.c_int64, c_void_p],
     "he_server_drain": [c_void_p],
+    "he_server_close_session": [c_void_p, c_u64],
     "he_server_replay": [c_void_p, c_u32, c_void_p, c_void_p, c_void_p, c_void_p, c_u32, c_void_p],
     "he_server_stats": [c_void_p, c_void_p],
     "he_server_destroy": [c_void_p],
@@ -480,7 +482,9 @@ class he_server_info(ctypes.Structure):
     _fields_ = [("completed", c_u64), ("rejected", c_u64), ("epochs", c_u64), ("mean_jobs_per_epoch", ctypes.c_double),
                 ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
                 ("max_s", ctypes.c_double), ("span_s", ctypes.c_double), ("peak_bytes", c_u64),
-                ("in_use_bytes", c_u64), ("single_epochs", c_u64)]
+                ("in_use_bytes", c_u64), ("single_epochs", c_u64), ("resident_hits", c_u64),
+                ("resident_misses", c_u64), ("evictions", c_u64), ("fwd_planes", c_u64), ("failed", c_u64),
+                ("resident_blocks", c_u64)]
 
 
 def he_server_create(mem_cap_bytes=64 << 30, mode=HE_SERVE_CONTINUOUS, device=0, arena_bytes=0, max_batch_jobs=0,
@@ -507,6 +511,10 @@ def he_server_wait(s, ticket, timeout_us=-1):
 
 def he_server_drain(s):
     _chk(_lib.he_server_drain(s), "he_server_drain")
+
+
+def he_server_close_session(s, session):
+    _chk(_lib.he_server_close_session(s, session), "he_server_close_session")
 
 
 def he_server_replay(s, ctxs, jobs, arrival_s, sessions=None, submit_flags=0):
