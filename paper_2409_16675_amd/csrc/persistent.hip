@@ -30,6 +30,14 @@ namespace he {
 // s_waitcnt immediate for gfx9-family: vmcnt = 0, expcnt and lgkmcnt left at their maxima
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// A pre task's outputs are written with device-coherent stores (agent-scope
+// relaxed atomic stores: written through this XCD's L2), so that once a wave's
+// stores have completed they are visible to every XCD without writing back the
+// whole L2, which a release would do after every task.
+__device__ __forceinline__ void publish(HE_GLOBAL uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class A>
 struct PTw {
   using T = typename A::Tw;
@@ -65,26 +73,26 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     const bool as_f64 = kF64 && jb.ct_f64;
     auto st = [&](int k, V v) {
       if constexpr (kF64) {
-        if (valid) dst[(uint32_t)k] = as_f64 ? __builtin_bit_cast(uint64_t, ar.reduce(v)) : ar.store(v);
+        if (valid) publish(dst + (uint32_t)k, as_f64 ? __builtin_bit_cast(uint64_t, ar.reduce(v)) : ar.store(v));
       } else {
-        if (valid) dst[(uint32_t)k] = ar.store(v);
+        if (valid) publish(dst + (uint32_t)k, ar.store(v));
       }
     };
-    ntt_forward<A, G, false, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+    ntt_forward<A, G, true, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
     auto st = [&](int k, V v) {
       if constexpr (kF64) {
-        if (valid) dst[(uint32_t)k] = __builtin_bit_cast(uint64_t, ar.reduce(v));
+        if (valid) publish(dst + (uint32_t)k, __builtin_bit_cast(uint64_t, ar.reduce(v)));
       } else {
-        if (valid) dst[(uint32_t)k] = ar.store(v);
+        if (valid) publish(dst + (uint32_t)k, ar.store(v));
       }
     };
     if (jb.pkind == PK_POLY) {
       const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
       auto ld = [&](int k) { return ar.load_signed(valid ? src[(uint32_t)k] : 0ll); };
-      ntt_forward<A, G, false, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+      ntt_forward<A, G, true, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
 #pragma unroll
@@ -96,7 +104,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
         scatter_weights<A, G>(ar, lds_g, tid_g, wp, pp, as_global((const int32_t *)jb.plain));
       }
       __syncthreads();
-      ntt_forward_tc<A, G, false, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g,
+      ntt_forward_tc<A, G, true, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g,
                                          LdsAt<typename A::V>{lds_g}, st);
     }
   } else {   // PT_MAC_INV: output plane (o, comp, i)
@@ -203,33 +211,46 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
   // Task source: the shared queue of pre tasks [0, xq.b[0]) first; then this
   // XCD's queue of dependent tasks (workgroups are dealt round-robin over the
   // XCDs, so blockIdx % 8 is the XCD), then the other XCDs' queues in turn.
-  // Thread 0 looks two tasks ahead: the next task's index, kind and job are
-  // known (loaded while the current task ran) and the one after is grabbed
-  // while the current task runs, so deciding on a dependency wait reads no
-  // memory.
+  // While a queue is deep, thread 0 looks two tasks ahead: the next task's
+  // index, kind and job are known (loaded while the current task ran) and the
+  // one after is grabbed while the current task runs, so deciding on a
+  // dependency wait reads no memory.  A grabbed task is this workgroup's, so
+  // near a queue's end (no more than twice the workgroups that share it left)
+  // nothing is reserved: a task is taken only when the previous one is done,
+  // and no workgroup sits idle while another holds two tasks in reserve.
   const uint32_t my_xcd = blockIdx.x % kXcds;
+  const uint32_t deep_pre = 2u * gridDim.x, deep_dep = 2u * (gridDim.x / kXcds);
+  constexpr uint32_t kNone = 0xFFFFFFFFu;   // no task reserved (above any task index and n_tasks)
   uint32_t q = 0;            // 0: pre queue; 1..8: dependent queue (my_xcd + q - 1) % 8
+  bool deep = false;         // the last grab left enough in its queue to reserve ahead
   auto grab = [&]() -> uint32_t {
     while (q <= (uint32_t)kXcds) {
       if (q == 0) {
         const uint32_t t0 = atomicAdd(head, 1u);
-        if (t0 < xq.b[0]) return t0;
+        if (t0 < xq.b[0]) {
+          deep = xq.b[0] - t0 > deep_pre;
+          return t0;
+        }
       } else {
         const uint32_t x = (my_xcd + q - 1) % kXcds;
         const uint32_t t0 = xq.b[x] + atomicAdd(ctl + CTL_XQ + 32 * x, 1u);
-        if (t0 < xq.b[x + 1]) return t0;
+        if (t0 < xq.b[x + 1]) {
+          deep = xq.b[x + 1] - t0 > deep_dep;
+          return t0;
+        }
       }
       ++q;
     }
+    deep = false;
     return n_tasks;
   };
-  uint32_t n1 = n_tasks, n2 = n_tasks, k1 = 0, j1 = 0;
+  uint32_t n1 = kNone, n2 = kNone, k1 = 0, j1 = 0;
   if (tid == 0) {
     n1 = grab();
     if (n1 < n_tasks) {
       k1 = tasks[n1].kind;
       j1 = tasks[n1].job;
-      n2 = grab();
+      if (deep) n2 = grab();
     }
   }
   for (uint32_t it = 0;; it ^= 1u) {
@@ -238,12 +259,20 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     // branch).  The slot of iteration it is written again two iterations later,
     // after the barrier that every thread reaches only after reading it here.
     if (tid == 0) {
-      const uint32_t t0 = n1, kind0 = k1, job0 = j1;
+      uint32_t t0 = n1, kind0 = k1, job0 = j1;
+      if (t0 == kNone) {   // nothing reserved: take a task now
+        t0 = grab();
+        if (t0 < n_tasks) {
+          kind0 = tasks[t0].kind;
+          job0 = tasks[t0].job;
+        }
+      }
       n1 = n2;
+      n2 = kNone;
       if (n1 < n_tasks) {
         k1 = tasks[n1].kind;
         j1 = tasks[n1].job;
-        n2 = grab();
+        if (deep) n2 = grab();
       }
       uint32_t w = 0;
       if (t0 < n_tasks && (kind0 & PT_WAIT))
@@ -301,12 +330,17 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
       }
     }
     if ((tk.kind & PT_KIND_MASK) != PT_MAC_INV) {
-      // every wave waits until its own global stores have reached L2 (the barrier
-      // alone orders LDS only); thread 0's release then writes L2 back and publishes
+      // every wave waits until its own device-coherent stores have completed
+      // (the barrier alone orders LDS only): the task's outputs are then visible
+      // on every XCD, and thread 0 counts the task done.  The strict mode adds
+      // a full release (an L2 writeback) before the count.
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       if (strict & 1u) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
-      if (tid == 0) __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) {
+        if (strict & 1u) __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        else __hip_atomic_fetch_add(done + tk.job, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     // (a dependent task needs no barrier here: the next task touches the plane
     // in LDS only after the next iteration's barrier)
