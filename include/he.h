@@ -228,8 +228,46 @@ he_status he_plan_get_info(const he_plan *plan, he_plan_info *info);
 /* Host copies of the term lists: output o sums terms [row[o], row[o+1]) of
  * ct_in[ct_idx[t]] (x) pt[pt_idx[t]].  row [n_ct_out+1], ct_idx/pt_idx [n_terms]. */
 he_status he_plan_terms(const he_plan *plan, int32_t *row, int32_t *ct_idx, int32_t *pt_idx);
-/* Device workspace he_corr_conv2d needs with these flags. */
+/* Device workspace he_corr_conv2d needs with these flags (HE_EINVAL for a host
+ * plan, which has no prime count: use he_layer_query). */
 he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes);
+
+/* Client-side plan (Section 3.3: the client packs its inputs into pi_x and
+ * reads the outputs back): the plan he_plan_create would give on a ring of
+ * degree N, with no context and no device memory.  he_plan_get_info,
+ * he_plan_terms, he_pack_input, he_extract_output, he_ppmul_ws_size and
+ * he_layer_query accept it; calls that run on a device refuse it (HE_EINVAL,
+ * "plan belongs to another context").  Free with he_plan_destroy.  Errors as
+ * he_plan_query. */
+he_status he_plan_create_host(uint32_t N, const he_conv_shape *shape, he_plan **out);
+
+/* Where a layer call packs raw weights into plaintext polynomials. */
+#define HE_PACK_NONE 0u   /* HE_PLAIN_POLY: the caller passes packed polynomials */
+#define HE_PACK_FUSED 1u  /* scattered in LDS inside the plaintext transform */
+#define HE_PACK_MEMORY 2u /* HE_UNFUSED: packed to workspace polynomials first */
+typedef struct {
+  uint64_t workspace_bytes; /* = he_workspace_size for these flags */
+  /* byte offsets of the workspace regions, UINT64_MAX where a region is absent */
+  uint64_t off_ct_hat;      /* transformed input ciphertexts (absent with HE_IN_NTT) */
+  uint64_t off_pt_poly;     /* packed plaintext polynomials (HE_PACK_MEMORY only) */
+  uint64_t off_pt_hat;      /* transformed plaintexts */
+  uint64_t off_acc;         /* accumulators of the unfused path (HE_UNFUSED without HE_OUT_NTT) */
+  uint64_t off_flag;        /* range-check flag (HE_VALIDATE) */
+  uint32_t fwd_ct_planes;   /* ciphertext planes forward transformed: n_ct_in*2*L (0 with HE_IN_NTT) */
+  uint32_t fwd_pt_planes;   /* plaintext planes forward transformed: n_pt*L */
+  uint32_t mac_planes;      /* output planes multiply-accumulated: n_ct_out*2*L */
+  uint32_t inv_planes;      /* output planes inverse transformed (0 with HE_OUT_NTT) */
+  uint32_t pack;            /* HE_PACK_* */
+  uint32_t reserved;
+} he_layer_info;
+/* Host-only setup of one he_corr_conv2d call with these flags on L primes (no
+ * device work): the same code runs inside the call before its first launch,
+ * so this returns the errors the call would return before launching --
+ * HE_EUNSUPPORTED for a weight-gradient plan without HE_PLAIN_POLY, HE_EINVAL
+ * when the plan's weight layout would place a packed weight outside the
+ * N-coefficient plane (every position is checked here, on the host).  L = 0
+ * takes a device plan's own prime count; a host plan needs L > 0. */
+he_status he_layer_query(const he_plan *plan, uint32_t L, uint32_t flags, he_layer_info *info);
 
 /* Server side of one layer (Section 3.2 online phase with the packing of Section 3.3):
  * transform the input ciphertexts, pack and transform the plaintexts, multiply-

@@ -64,6 +64,48 @@ def build(verbose=False, incremental=False):
     return LIB
 
 
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the host sources (the
+# device code and its launch glue come from the regular objects), linked as
+# _build_san/libhe.so: the host-side tests run against it with the sanitizer
+# runtime preloaded (HE_LIBRARY selects it).  Every -fsanitize applies to the
+# host pass only.
+SAN_BUILD = os.path.join(ROOT, "_build_san")
+SAN_LIB = os.path.join(SAN_BUILD, "libhe.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-shared-libasan",
+             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build_sanitized(verbose=False):
+    """Link the sanitized library (build() first: the device objects are reused)."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    host = [s for s in SOURCES if s.endswith(".cpp")]
+    flags = [f for f in FLAGS if f != "-O3"] + SAN_FLAGS
+
+    def comp(src):
+        out = os.path.join(SAN_BUILD, src + ".o")
+        r = subprocess.run([HIPCC] + flags + ["-c", os.path.join(CSRC, src), "-o", out], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc (sanitized) failed for %s:\n%s" % (src, r.stderr[-8000:]))
+        return out
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(host))) as ex:
+        objs = list(ex.map(comp, host))
+    objs += [os.path.join(BUILD, s + ".o") for s in SOURCES if not s.endswith(".cpp")]
+    tmp = SAN_LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libasan", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stderr[-8000:])
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print(SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True, incremental="--incremental" in sys.argv)
+    if "--sanitized" in sys.argv:
+        build_sanitized(verbose=True)
     sys.exit(0)

@@ -95,18 +95,24 @@ static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
   pj.pkind = (f & HE_PLAIN_POLY) ? PK_POLY
                                  : (in.kind == HE_KIND_FC ? PK_FC : (in.kind == HE_KIND_DX ? PK_CONV_DX : PK_CONV));
   if (in.kind == HE_KIND_DW && pj.pkind != PK_POLY) return fail(HE_EUNSUPPORTED, "weight-gradient jobs need HE_PLAIN_POLY");
-  pj.M = p.eq.M;
-  pj.C = p.eq.C;
-  pj.h = p.eq.h;
-  pj.O = in.O;
-  pj.S = in.S;
-  pj.Cw = in.Cw;
-  pj.cb = in.cb;
-  pj.n_in = p.shape.n_in;
-  pj.n_out = p.shape.n_out;
-  pj.n_iw = in.n_iw;
-  pj.n_ow = in.n_ow;
-  pj.in_ct = in.n_iw ? (p.shape.n_in + in.n_iw - 1) / in.n_iw : 0;
+  if (pj.pkind != PK_POLY) {
+    // the layout the in-LDS scatter follows, its positions checked on the host
+    WPack wp;
+    he_status s = weight_pack(p, wp);
+    if (s != HE_OK) return s;
+    pj.M = wp.M;
+    pj.C = wp.C;
+    pj.h = wp.h;
+    pj.O = wp.O;
+    pj.S = wp.S;
+    pj.Cw = wp.Cw;
+    pj.cb = wp.cb;
+    pj.n_in = wp.n_in;
+    pj.n_out = wp.n_out;
+    pj.n_iw = wp.n_iw;
+    pj.n_ow = wp.n_ow;
+    pj.in_ct = wp.in_ct;
+  }
   return HE_OK;
 }
 

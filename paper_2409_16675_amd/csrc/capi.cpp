@@ -246,7 +246,7 @@ static size_t al256p(size_t b) { return (b + 255) & ~(size_t)255; }
 he_status he_ppmul_ws_size(const he_plan *plan, uint32_t flags, size_t *bytes) {
   if (!plan || !bytes) return fail(HE_EINVAL, "null argument");
   const he_plan_info &in = plan->p.info;
-  const size_t plane = (size_t)plan->ctx->N * 8;
+  const size_t plane = (size_t)in.N * 8;
   *bytes = al256p((size_t)in.n_ct_in * plane) + al256p((size_t)in.n_pt * plane) + ((flags & HE_VALIDATE) ? 256 : 0);
   return HE_OK;
 }
@@ -384,18 +384,38 @@ struct WsLayout {
   size_t ct_hat = 0, pt_poly = 0, pt_hat = 0, acc = 0, flag = 0, total = 0;
 };
 
-static WsLayout ws_layout(const Ctx &c, const Plan &p, uint32_t flags) {
-  WsLayout w;
+// Host setup of one layer call (no device work): the workspace layout, where
+// raw weights are packed, and the planes each stage covers.  he_corr_conv2d
+// (and its seeded and allocation-free forms) runs exactly this before its first
+// launch; he_layer_query reports it for a host plan.
+struct LayerSetup {
+  WsLayout ws;
+  uint32_t pack = HE_PACK_NONE;
+  WPack wp{};
+  uint32_t fwd_ct = 0, fwd_pt = 0, mac = 0, inv = 0;
+};
+
+static he_status layer_setup(uint32_t N, uint32_t L, const Plan &p, uint32_t flags, LayerSetup &ls) {
   const he_plan_info &in = p.info;
+  ls = LayerSetup{};
+  if (!L) return fail(HE_EINVAL, "no primes");
+  if (in.kind == HE_KIND_DW && !(flags & HE_PLAIN_POLY))
+    return fail(HE_EUNSUPPORTED, "weight-gradient plaintexts are passed as packed polynomials (HE_PLAIN_POLY)");
+  ls.pack = (flags & HE_PLAIN_POLY) ? HE_PACK_NONE : ((flags & HE_UNFUSED) ? HE_PACK_MEMORY : HE_PACK_FUSED);
+  if (ls.pack != HE_PACK_NONE) {
+    he_status s = weight_pack(p, ls.wp);
+    if (s != HE_OK) return s;
+  }
+  WsLayout &w = ls.ws;
   size_t off = 0;
-  const size_t plane = (size_t)c.L * c.N * 8;
+  const size_t plane = (size_t)L * N * 8;
   if (!(flags & HE_IN_NTT)) {
     w.ct_hat = off;
     off += al256((size_t)in.n_ct_in * 2 * plane);
   }
-  if (!(flags & HE_PLAIN_POLY)) {
+  if (ls.pack == HE_PACK_MEMORY) {
     w.pt_poly = off;
-    off += al256((size_t)in.n_pt * c.N * 8);
+    off += al256((size_t)in.n_pt * N * 8);
   }
   w.pt_hat = off;
   off += al256((size_t)in.n_pt * plane);
@@ -408,19 +428,66 @@ static WsLayout ws_layout(const Ctx &c, const Plan &p, uint32_t flags) {
     off += 256;
   }
   w.total = off;
-  return w;
+  ls.fwd_ct = (flags & HE_IN_NTT) ? 0u : in.n_ct_in * 2 * L;
+  ls.fwd_pt = in.n_pt * L;
+  ls.mac = in.n_ct_out * 2 * L;
+  ls.inv = (flags & HE_OUT_NTT) ? 0u : in.n_ct_out * 2 * L;
+  return HE_OK;
 }
 
 he_status he_workspace_size(const he_plan *plan, uint32_t flags, size_t *bytes) {
   if (!plan || !bytes) return fail(HE_EINVAL, "null argument");
-  *bytes = ws_layout(*plan->ctx, plan->p, flags).total;
+  if (!plan->ctx) return fail(HE_EINVAL, "a host plan has no context: he_layer_query takes the prime count");
+  LayerSetup ls;
+  he_status s = layer_setup(plan->ctx->N, plan->ctx->L, plan->p, flags, ls);
+  if (s != HE_OK) return s;
+  *bytes = ls.ws.total;
+  return HE_OK;
+}
+
+he_status he_plan_create_host(uint32_t N, const he_conv_shape *shape, he_plan **out) {
+  if (!shape || !out) return fail(HE_EINVAL, "null argument");
+  *out = nullptr;
+  if (N < 16 || N > 32768 || (N & (N - 1))) return fail(HE_EINVAL, "N must be a power of two in [16, 2^15]");
+  Ctx c;
+  c.N = N;
+  he_plan *p = new he_plan{nullptr, Plan{}};
+  he_status s = make_plan(c, *shape, p->p);
+  if (s != HE_OK) {
+    delete p;
+    return s;
+  }
+  p->p.device = -1;
+  *out = p;
+  return HE_OK;
+}
+
+he_status he_layer_query(const he_plan *plan, uint32_t L, uint32_t flags, he_layer_info *info) {
+  if (!plan || !info) return fail(HE_EINVAL, "null argument");
+  if (plan->ctx && L && L != plan->ctx->L) return fail(HE_EINVAL, "prime count differs from the plan's context");
+  if (plan->ctx) L = plan->ctx->L;
+  LayerSetup ls;
+  he_status s = layer_setup(plan->p.info.N, L, plan->p, flags, ls);
+  if (s != HE_OK) return s;
+  const uint64_t none = ~0ull;
+  const bool ct = !(flags & HE_IN_NTT), acc = (flags & HE_UNFUSED) && !(flags & HE_OUT_NTT);
+  *info = he_layer_info{ls.ws.total,
+                        ct ? ls.ws.ct_hat : none,
+                        ls.pack == HE_PACK_MEMORY ? ls.ws.pt_poly : none,
+                        ls.ws.pt_hat,
+                        acc ? ls.ws.acc : none,
+                        (flags & HE_VALIDATE) ? ls.ws.flag : none,
+                        ls.fwd_ct, ls.fwd_pt, ls.mac, ls.inv, ls.pack, 0u};
   return HE_OK;
 }
 
 }  // extern "C"
 
 namespace he {
-size_t layer_ws_bytes(const Ctx &c, const Plan &p, uint32_t flags) { return ws_layout(c, p, flags).total; }
+size_t layer_ws_bytes(const Ctx &c, const Plan &p, uint32_t flags) {
+  LayerSetup ls;
+  return layer_setup(c.N, c.L, p, flags, ls) == HE_OK ? ls.ws.total : 0;
+}
 he_status run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
                     uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st, const uint64_t *seed = nullptr);
 }  // namespace he
@@ -455,7 +522,10 @@ he_status he_expand_c1(he_ctx *ctx, const uint64_t *seed, uint32_t first_ct, uin
 he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, const void *plain, uint64_t *ct_out,
                         uint32_t flags, void *ws, size_t ws_bytes, hipStream_t st, const uint64_t *seed) {
   const he_plan_info &in = p.info;
-  const WsLayout L = ws_layout(c, p, flags);
+  LayerSetup ls;
+  he_status s0 = layer_setup(c.N, c.L, p, flags, ls);
+  if (s0 != HE_OK) return s0;
+  const WsLayout &L = ls.ws;
   if (ws_bytes < L.total || (L.total && !ws)) return fail(HE_ENOMEM, "workspace too small");
   char *w = (char *)ws;
   if (flags & HE_VALIDATE) {
@@ -463,33 +533,11 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
     he_status s = validate(c, ct_in, (size_t)in.n_ct_in * (seed ? 1 : 2) * c.L, w + L.flag, st);
     if (s != HE_OK) return s;
   }
-  if ((flags & HE_PLAIN_POLY) == 0 && in.kind == HE_KIND_DW)
-    return fail(HE_EUNSUPPORTED, "weight-gradient plaintexts are passed as packed polynomials (HE_PLAIN_POLY)");
   // weights packed in LDS inside the plaintext transform (fused path), or
-  // packed to memory first (unfused baseline, or polynomials given)
+  // packed to memory first (unfused baseline), or polynomials given
   uint64_t *pt_hat = (uint64_t *)(w + L.pt_hat);
-  const bool pack_fused = !(flags & (HE_PLAIN_POLY | HE_UNFUSED));
-  WPack wp{};
-  if (!pack_fused) {
-    // weight-gradient layers (polynomials given) and the unfused baseline pack
-    // nothing here; the layout below is for raw conv, input-gradient or FC weights
-  } else if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX) {
-    wp.kind = in.kind == HE_KIND_DX ? WP_CONV_DX : WP_CONV;
-    wp.M = p.eq.M;
-    wp.C = p.eq.C;
-    wp.h = p.eq.h;
-    wp.O = in.O;
-    wp.S = in.S;
-    wp.Cw = in.Cw;
-    wp.cb = in.cb;
-  } else if (in.kind == HE_KIND_FC) {
-    wp.kind = WP_FC;
-    wp.n_out = p.shape.n_out;
-    wp.n_in = p.shape.n_in;
-    wp.n_iw = in.n_iw;
-    wp.n_ow = in.n_ow;
-    wp.in_ct = (p.shape.n_in + in.n_iw - 1) / in.n_iw;
-  }
+  const bool pack_fused = ls.pack == HE_PACK_FUSED;
+  const WPack &wp = ls.wp;
   // 1. transform the input ciphertexts (2. and the packed plaintexts, in the
   // same launch when both are transformed here)
   const uint64_t *ct_hat = ct_in;
@@ -530,16 +578,16 @@ he_status he::run_layer(const Ctx &c, const Plan &p, const uint64_t *ct_in, cons
                  [&] { return launch_ntt_fwd_pack(c, c.s_fwd, pt_hat, (const int32_t *)plain, wp, in.n_pt, st); }),
            "conv pack + fwd pt");
   const int64_t *polys = (const int64_t *)plain;
-  if (!pack_fused && !(flags & HE_PLAIN_POLY)) {
+  if (ls.pack == HE_PACK_MEMORY) {
     int64_t *pp = (int64_t *)(w + L.pt_poly);
     HIPCHK(timed(c, st, KK_PACK, [&] {
              hipError_t e = launch_zero_i64(pp, (size_t)in.n_pt * c.N, st);
              if (e != hipSuccess) return e;
-             if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX)
-               return launch_pack_conv_w(pp, (const int32_t *)plain, p.eq.M, p.eq.C, p.eq.h, in.O, in.S, in.Cw,
-                                         in.cb, c.N, in.kind == HE_KIND_DX, st);
-             return launch_pack_fc_w(pp, (const int32_t *)plain, p.shape.n_out, p.shape.n_in, in.n_iw, in.n_ow,
-                                     (p.shape.n_in + in.n_iw - 1) / in.n_iw, c.N, st);
+             if (wp.kind != WP_FC)
+               return launch_pack_conv_w(pp, (const int32_t *)plain, wp.M, wp.C, wp.h, wp.O, wp.S, wp.Cw, wp.cb, c.N,
+                                         wp.kind == WP_CONV_DX, st);
+             return launch_pack_fc_w(pp, (const int32_t *)plain, wp.n_out, wp.n_in, wp.n_iw, wp.n_ow, wp.in_ct, c.N,
+                                     st);
            }),
            "pack");
     polys = pp;

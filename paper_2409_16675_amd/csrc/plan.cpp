@@ -38,6 +38,48 @@ he_status make_plan(const Ctx &c, const he_conv_shape &s, Plan &p) {
   return HE_OK;
 }
 
+he_status weight_pack(const Plan &p, WPack &wp) {
+  const he_plan_info &in = p.info;
+  const uint64_t N = in.N;
+  wp = WPack{};
+  if (in.kind == HE_KIND_CONV || in.kind == HE_KIND_DX) {
+    wp.kind = in.kind == HE_KIND_DX ? WP_CONV_DX : WP_CONV;
+    wp.M = p.eq.M;
+    wp.C = p.eq.C;
+    wp.h = p.eq.h;
+    wp.O = in.O;
+    wp.S = in.S;
+    wp.Cw = in.Cw;
+    wp.cb = in.cb;
+    if (!wp.M || !wp.C || !wp.h || !wp.Cw || !wp.cb) return fail(HE_EINVAL, "weight layout: empty conv block");
+    if ((uint64_t)wp.cb * wp.Cw < wp.C) return fail(HE_EINVAL, "weight layout: channel blocks miss channels");
+    if (in.n_pt != wp.M * wp.cb) return fail(HE_EINVAL, "weight layout: plaintext count is not M x blocks");
+    // tap (a, b) of the block's first channel sits at (h-1-a) O + (h-1-b); channel
+    // cc > 0 of the block at N - cc S + that (negated): all inside [0, N) when the
+    // largest tap position lies below S and N, and (channels - 1) S <= N
+    const uint64_t top = (uint64_t)(wp.h - 1) * wp.O + (wp.h - 1);
+    const uint64_t chans = wp.Cw < wp.C ? wp.Cw : wp.C;
+    if (top >= N) return fail(HE_EINVAL, "weight layout: kernel taps beyond the ring degree");
+    if (chans > 1 && (top >= wp.S || (chans - 1) * wp.S > N))
+      return fail(HE_EINVAL, "weight layout: channel slots overlap or leave the plane");
+  } else if (in.kind == HE_KIND_FC) {
+    wp.kind = WP_FC;
+    wp.n_out = p.shape.n_out;
+    wp.n_in = p.shape.n_in;
+    wp.n_iw = in.n_iw;
+    wp.n_ow = in.n_ow;
+    if (!wp.n_out || !wp.n_in || !wp.n_iw || !wp.n_ow) return fail(HE_EINVAL, "weight layout: empty FC chunk");
+    wp.in_ct = (wp.n_in + wp.n_iw - 1) / wp.n_iw;
+    // W[ko n_ow + ii][ki n_iw + jj] sits at ii n_iw + n_iw - 1 - jj < n_ow n_iw
+    if ((uint64_t)wp.n_ow * wp.n_iw > N) return fail(HE_EINVAL, "weight layout: FC chunk beyond the ring degree");
+    if (in.n_pt != ((wp.n_out + wp.n_ow - 1) / wp.n_ow) * wp.in_ct)
+      return fail(HE_EINVAL, "weight layout: plaintext count is not output x input chunks");
+  } else {
+    return fail(HE_EUNSUPPORTED, "weight-gradient plaintexts are passed as packed polynomials (HE_PLAIN_POLY)");
+  }
+  return HE_OK;
+}
+
 static he_status make_plan_geom(const Ctx &c, const he_conv_shape &s, Plan &p) {
   p.shape = s;
   he_plan_info &in = p.info;

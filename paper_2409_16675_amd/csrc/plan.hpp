@@ -24,6 +24,13 @@ struct Plan {
 
 he_status make_plan(const Ctx &c, const he_conv_shape &s, Plan &p);
 
+// Layout of a conv, input-gradient or FC plan's raw weights in its plaintext
+// polynomials (what scatter_weights and the packing kernels follow), checked on
+// the host: every packed position lies inside the N-coefficient plane and every
+// weight index inside the weight tensor, else HE_EINVAL.  Weight-gradient plans
+// take packed polynomials: HE_EUNSUPPORTED.
+he_status weight_pack(const Plan &p, WPack &wp);
+
 }  // namespace he
 
 struct he_plan {

@@ -12,10 +12,11 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libhe.so")
+# HE_LIBRARY selects another build of the same library (the host-sanitizer build)
+LIB_PATH = os.environ.get("HE_LIBRARY") or os.path.join(_PKG, "libhe.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libhe.so is not built (run paper_2409_16675_amd.build.build() or __graft_entry__.build())")
+    raise ImportError("%s is not built (run paper_2409_16675_amd.build.build() or __graft_entry__.build())" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -23,6 +24,7 @@ HE_OK = 0
 HE_EINVAL, HE_EUNSUPPORTED, HE_ENOMEM, HE_EDEVICE, HE_ERANGE, HE_EBUSY, HE_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 HE_ARITH_AUTO, HE_ARITH_F64, HE_ARITH_U64 = 0, 1, 2
 HE_IN_NTT, HE_OUT_NTT, HE_ACCUMULATE, HE_VALIDATE, HE_PLAIN_POLY, HE_UNFUSED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+HE_PACK_NONE, HE_PACK_FUSED, HE_PACK_MEMORY = 0, 1, 2
 HE_IN_RESIDENT = 0x40
 HE_KIND_CONV, HE_KIND_DW, HE_KIND_FC, HE_KIND_DX = 0, 1, 2, 3
 HE_PREPARE_PPMUL, HE_PREPARE_CCMUL = 0x1, 0x2
@@ -51,6 +53,12 @@ class he_plan_info(ctypes.Structure):
                  "n_ct_out", "n_terms", "Hw", "Ww", "tiles")]
 
 
+class he_layer_info(ctypes.Structure):
+    _fields_ = [("workspace_bytes", c_u64), ("off_ct_hat", c_u64), ("off_pt_poly", c_u64), ("off_pt_hat", c_u64),
+                ("off_acc", c_u64), ("off_flag", c_u64), ("fwd_ct_planes", c_u32), ("fwd_pt_planes", c_u32),
+                ("mac_planes", c_u32), ("inv_planes", c_u32), ("pack", c_u32), ("reserved", c_u32)]
+
+
 _SIGS = {
     "he_ctx_create": [ctypes.POINTER(he_params), ctypes.POINTER(c_void_p)],
     "he_ctx_destroy": [c_void_p],
@@ -69,6 +77,8 @@ _SIGS = {
     "he_plan_destroy": [c_void_p],
     "he_plan_get_info": [c_void_p, ctypes.POINTER(he_plan_info)],
     "he_plan_query": [c_u32, ctypes.POINTER(he_conv_shape), ctypes.POINTER(he_plan_info)],
+    "he_plan_create_host": [c_u32, ctypes.POINTER(he_conv_shape), ctypes.POINTER(c_void_p)],
+    "he_layer_query": [c_void_p, c_u32, c_u32, ctypes.POINTER(he_layer_info)],
     "he_ccmul_ws_size": [c_void_p, c_u32, c_u32, c_u32, c_u32, c_u32, ctypes.POINTER(c_size)],
     "he_ccmul": [c_void_p, c_void_p, c_u32, c_void_p, c_u32, i32p, i32p, i32p, c_u32, c_void_p, c_void_p, c_u32,
                  c_void_p, c_size, c_void_p],
@@ -270,6 +280,21 @@ def he_plan_query(N, kind, B=1, C=0, M=0, H=0, W=0, h=0, P=0, n_in=0, n_out=0, s
     i = he_plan_info()
     _chk(_lib.he_plan_query(N, ctypes.byref(s), ctypes.byref(i)), "he_plan_query")
     return {n: getattr(i, n) for n, _ in he_plan_info._fields_}
+
+
+def he_plan_create_host(N, kind, B=1, C=0, M=0, H=0, W=0, h=0, P=0, n_in=0, n_out=0, stride=0):
+    """Client-side plan on ring degree N: no context, no device memory."""
+    s = he_conv_shape(kind, B, C, M, H, W, h, P, n_in, n_out, stride)
+    out = c_void_p()
+    _chk(_lib.he_plan_create_host(N, ctypes.byref(s), ctypes.byref(out)), "he_plan_create_host")
+    return out.value
+
+
+def he_layer_query(plan, L=0, flags=0):
+    """Host-only setup of one layer call: workspace regions, planes per stage, packing."""
+    i = he_layer_info()
+    _chk(_lib.he_layer_query(plan, L, flags, ctypes.byref(i)), "he_layer_query")
+    return {n: getattr(i, n) for n, _ in he_layer_info._fields_ if n != "reserved"}
 
 
 def he_plan_terms(plan):
@@ -581,13 +606,13 @@ class Context:
 
 
 class Plan:
-    """Owns an he_plan handle."""
+    """Owns an he_plan handle: on a context, or (ctx None, N given) a host plan."""
 
-    def __init__(self, ctx, kind, **shape):
+    def __init__(self, ctx, kind, N=None, **shape):
         self.ctx = ctx
         self.shape = dict(shape)
         self.kind = kind
-        self.h = he_plan_create(ctx.h, kind, **shape)
+        self.h = he_plan_create(ctx.h, kind, **shape) if ctx is not None else he_plan_create_host(N, kind, **shape)
         self.info = he_plan_get_info(self.h)
 
     def workspace_size(self, flags=0):

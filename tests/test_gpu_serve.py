@@ -231,9 +231,9 @@ def test_kept_blocks_are_evicted_rather_than_blocking_admission(gpu_lib, ctxs):
     # no running job reads (waits are bounded so a stuck server fails the test)
     he = gpu_lib
     big = [make_job(he, ctxs, 2, 2, 1000 + k) for k in range(4)]   # conv 32 -> 64 @ 8x8 at N = 16384
-    # footprint 106 MB (41 MB workspace, kept afterwards, + 1 MB in + 64 MB out):
-    # a kept block and the next job (147 MB) exceed the cap
-    cap = 140 << 20
+    # footprint 98 MB (33 MB workspace, kept afterwards, + 1 MB in + 64 MB out):
+    # a kept block and the next job (131 MB) exceed the cap
+    cap = 128 << 20
     srv = he.he_server_create(mem_cap_bytes=cap, slots=2, arena_bytes=256 << 20, session_jobs=0)
     tickets = [he.he_server_submit(srv, j["ctx"].h, j["plan"].h, j["d_ct"], j["d_w"], j["out"], session=20 + k,
                                    submit_flags=he.HE_SERVE_KEEP_RESIDENT) for k, j in enumerate(big)]
