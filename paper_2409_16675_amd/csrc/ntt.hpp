@@ -620,7 +620,9 @@ __device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typ
 // With longer runs a store instruction would touch four times the lines of a
 // linear store, each a quarter filled, which measured slower than the round
 // trip: the pass goes to LDS and the plane is written in linear order.
-template <class A, class G, bool PF = true, bool CANON = true, class TwP, class Ld2, class St>
+// LINEAR takes that round trip at any R: for callers whose stores are written
+// through to memory, where a partly filled line costs a partial write.
+template <class A, class G, bool PF = true, bool CANON = true, bool LINEAR = false, class TwP, class Ld2, class St>
 __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typename A::V *lds, Ld2 ld2, St st) {
   static_assert(G::NPASS >= 2, "at least two passes");
   using V = typename A::V;
@@ -644,7 +646,7 @@ __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typ
     if constexpr (CANON) st(i, ar.store(v));
     else st(i, v);
   };
-  if constexpr (G::r(G::NPASS - 1) <= 2) {
+  if constexpr (!LINEAR && G::r(G::NPASS - 1) <= 2) {
     auto st_out = [&](int t, int c, V v) { out(t + c, v); };
     fwd_pass<A, G, G::NPASS - 1>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
   } else {
@@ -655,9 +657,9 @@ __device__ __forceinline__ void ntt_forward_tc(const A &ar, TwP tw, int tid, typ
   }
 }
 // The same with ld(i) reading coefficient i.
-template <class A, class G, bool PF = true, bool CANON = true, class TwP, class Ld, class St>
+template <class A, class G, bool PF = true, bool CANON = true, bool LINEAR = false, class TwP, class Ld, class St>
 __device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typename A::V *lds, Ld ld, St st) {
-  ntt_forward_tc<A, G, PF, CANON>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
+  ntt_forward_tc<A, G, PF, CANON, LINEAR>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
 }
 
 // Whole inverse transform of values v already in registers in the layout of

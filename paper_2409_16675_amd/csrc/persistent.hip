@@ -33,7 +33,9 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 // A pre task's outputs are written with device-coherent stores (agent-scope
 // relaxed atomic stores: written through this XCD's L2), so that once a wave's
 // stores have completed they are visible to every XCD without writing back the
-// whole L2, which a release would do after every task.
+// whole L2, which a release would do after every task.  Written through, a
+// partly filled line costs a partial write: the transforms feeding these
+// stores end with a pass through LDS and store whole lines in linear order.
 __device__ __forceinline__ void publish(HE_GLOBAL uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -78,7 +80,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
         if (valid) publish(dst + (uint32_t)k, ar.store(v));
       }
     };
-    ntt_forward<A, G, true, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+    ntt_forward<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (kind == PT_PT) {
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
@@ -92,7 +94,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     if (jb.pkind == PK_POLY) {
       const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
       auto ld = [&](int k) { return ar.load_signed(valid ? src[(uint32_t)k] : 0ll); };
-      ntt_forward<A, G, true, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+      ntt_forward<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
 #pragma unroll
@@ -104,7 +106,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
         scatter_weights<A, G>(ar, lds_g, tid_g, wp, pp, as_global((const int32_t *)jb.plain));
       }
       __syncthreads();
-      ntt_forward_tc<A, G, true, false>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g,
+      ntt_forward_tc<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g,
                                          LdsAt<typename A::V>{lds_g}, st);
     }
   } else {   // PT_MAC_INV: output plane (o, comp, i)
