@@ -40,6 +40,19 @@ __device__ __forceinline__ void publish(HE_GLOBAL uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A workgroup barrier that orders LDS only: each wave's LDS accesses before it
+// have completed, while its global loads and stores may still be in flight
+// (__syncthreads would also wait for every outstanding global access, here
+// the previous task's output stores).  The compiler fences keep LDS accesses
+// from moving across it; global ordering in the task loop comes from the
+// explicit waits, counters and acquires around it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <class A>
 struct PTw {
   using T = typename A::Tw;
@@ -50,9 +63,9 @@ struct PTw {
 // One task on one plane group member.  G: geometry with E = 16.  `valid` is
 // false for a group member past the end of the task's plane range: it runs
 // the same barriers but reads zeros and stores nothing.
-template <class A, int LOGN, int LOGE>
+template <class A, int LOGN, int LOGE, class Hook>
 __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int tid_g, int group,
-                                         typename A::V *lds_g) {
+                                         typename A::V *lds_g, Hook hook) {
   using G = Geo<LOGN, LOGN - LOGE>;
   using V = typename A::V;
   const uint32_t plane = tk.first + (uint32_t)group;
@@ -68,6 +81,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   // integers, canonical residues.
   constexpr bool kF64 = std::is_same<A, ArF64>::value;
   if (kind == PT_FWD_CT) {
+    hook();
     const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
     auto ld = [&](int k) { return ar.load(valid ? src[(uint32_t)k] : 0ull); };
@@ -82,6 +96,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     };
     ntt_forward<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
   } else if (kind == PT_PT) {
+    hook();
     const uint32_t pp = valid ? plane / L : 0;
     HE_GLOBAL uint64_t *dst = as_global(jb.pt_hat) + (size_t)plane * G::N;
     auto st = [&](int k, V v) {
@@ -150,6 +165,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
 #pragma unroll
       for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
     }
+    hook();   // the operands are consumed: the next claim has long returned
     // (the first pass's twiddles are loaded here, not with the operands: held
     // across the products they would push the kernel past its register budget)
     const auto twi = PTw<A>::inv(jb) + (size_t)i * G::N;
@@ -201,11 +217,12 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     const PTask *__restrict__ tasks, uint32_t n_tasks, XQ xq, const PJob *__restrict__ jobs, uint32_t n_jobs,
     uint32_t *__restrict__ ctl, uint32_t spin_limit, uint32_t strict) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_task[2], s_wait[2];   // used in turn by consecutive iterations
-  __shared__ uint32_t s_ready[64];   // acquired jobs (bitmap, jobs < 2048); touched by thread 0 only
+  __shared__ uint32_t s_task[2];     // the next task, used in turn by consecutive iterations
+  __shared__ uint32_t s_ready[64];   // acquired jobs (bitmap, jobs < 2048); written by thread 0 only
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
   const int tid = threadIdx.x;
   uint32_t *head = ctl + CTL_HEAD, *err = ctl + CTL_ERR, *done = ctl + CTL_DONE;
+  (void)n_tasks;
   if (tid == 0)
     for (int k = 0; k < 64; ++k) s_ready[k] = 0u;
   // (The caches are invalidated before the launch and written back after it by
@@ -213,83 +230,65 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
   // Task source: the shared queue of pre tasks [0, xq.b[0]) first; then this
   // XCD's queue of dependent tasks (workgroups are dealt round-robin over the
   // XCDs, so blockIdx % 8 is the XCD), then the other XCDs' queues in turn.
-  // While a queue is deep, thread 0 looks two tasks ahead: the next task's
-  // index, kind and job are known (loaded while the current task ran) and the
-  // one after is grabbed while the current task runs, so deciding on a
-  // dependency wait reads no memory.  A grabbed task is this workgroup's, so
-  // near a queue's end (no more than twice the workgroups that share it left)
-  // nothing is reserved: a task is taken only when the previous one is done,
-  // and no workgroup sits idle while another holds two tasks in reserve.
+  // Thread 0 claims the next task from a queue's counter at the start of the
+  // current one and reads the claim back inside it, before the task's stores
+  // (run_task's hook), so the claim's latency hides behind the task and no
+  // global access is outstanding across the loop's barrier: that barrier
+  // orders LDS only and leaves the previous task's stores in flight.
   const uint32_t my_xcd = blockIdx.x % kXcds;
-  const uint32_t deep_pre = 2u * gridDim.x, deep_dep = 2u * (gridDim.x / kXcds);
-  constexpr uint32_t kNone = 0xFFFFFFFFu;   // no task reserved (above any task index and n_tasks)
-  uint32_t q = 0;            // 0: pre queue; 1..8: dependent queue (my_xcd + q - 1) % 8
-  bool deep = false;         // the last grab left enough in its queue to reserve ahead
-  auto grab = [&]() -> uint32_t {
-    while (q <= (uint32_t)kXcds) {
-      if (q == 0) {
-        const uint32_t t0 = atomicAdd(head, 1u);
-        if (t0 < xq.b[0]) {
-          deep = xq.b[0] - t0 > deep_pre;
-          return t0;
-        }
-      } else {
-        const uint32_t x = (my_xcd + q - 1) % kXcds;
-        const uint32_t t0 = xq.b[x] + atomicAdd(ctl + CTL_XQ + 32 * x, 1u);
-        if (t0 < xq.b[x + 1]) {
-          deep = xq.b[x + 1] - t0 > deep_dep;
-          return t0;
-        }
-      }
-      ++q;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;   // no task left
+  uint32_t q = 0;   // thread 0: the queue claimed from (0 pre; 1..8 dependent queue (my_xcd + q - 1) % 8)
+  auto queue = [&](uint32_t qq, uint32_t &lo, uint32_t &hi) -> uint32_t * {
+    if (qq == 0) {
+      lo = 0, hi = xq.b[0];
+      return head;
     }
-    deep = false;
-    return n_tasks;
+    const uint32_t x = (my_xcd + qq - 1) % kXcds;
+    lo = xq.b[x], hi = xq.b[x + 1];
+    return ctl + CTL_XQ + 32 * x;
   };
-  uint32_t n1 = kNone, n2 = kNone, k1 = 0, j1 = 0;
-  if (tid == 0) {
-    n1 = grab();
-    if (n1 < n_tasks) {
-      k1 = tasks[n1].kind;
-      j1 = tasks[n1].job;
-      if (deep) n2 = grab();
+  auto issue = [&]() -> uint32_t {   // thread 0: start a claim on the current queue
+    uint32_t lo, hi;
+    return q <= (uint32_t)kXcds ? atomicAdd(queue(q, lo, hi), 1u) : 0u;
+  };
+  auto finish = [&](uint32_t pos) -> uint32_t {   // thread 0: the claimed task, or the next queue's
+    while (q <= (uint32_t)kXcds) {
+      uint32_t lo, hi;
+      queue(q, lo, hi);
+      if (lo + pos < hi) return lo + pos;
+      if (++q > (uint32_t)kXcds) break;
+      pos = atomicAdd(queue(q, lo, hi), 1u);
     }
-  }
+    return kNone;
+  };
+  uint32_t ready_job = 0xFFFFFFFFu;   // job of the last dependent task (acquired); workgroup-uniform
+  if (tid == 0) s_task[0] = finish(issue());
   for (uint32_t it = 0;; it ^= 1u) {
-    // thread 0 takes the next task and decides, for the whole workgroup, whether
-    // it must wait for the job's pre tasks (so every thread takes the same
-    // branch).  The slot of iteration it is written again two iterations later,
-    // after the barrier that every thread reaches only after reading it here.
-    if (tid == 0) {
-      uint32_t t0 = n1, kind0 = k1, job0 = j1;
-      if (t0 == kNone) {   // nothing reserved: take a task now
-        t0 = grab();
-        if (t0 < n_tasks) {
-          kind0 = tasks[t0].kind;
-          job0 = tasks[t0].job;
-        }
-      }
-      n1 = n2;
-      n2 = kNone;
-      if (n1 < n_tasks) {
-        k1 = tasks[n1].kind;
-        j1 = tasks[n1].job;
-        if (deep) n2 = grab();
-      }
-      uint32_t w = 0;
-      if (t0 < n_tasks && (kind0 & PT_WAIT))
-        w = (!(strict & 1u) && job0 < 2048 && ((s_ready[job0 >> 5] >> (job0 & 31)) & 1u)) ? 0u : 1u;
-      s_task[it] = t0;
-      s_wait[it] = w;
-    }
-    __syncthreads();
-    // the task index and the wait decision are workgroup-uniform: keep them (and
-    // the task and job fields loaded through them) in scalar registers
+    // (the slot of iteration it was written by thread 0 during the previous
+    // task; it is written again during the next one, after the barrier below
+    // that every thread passes only after reading it)
+    lds_barrier();
     const uint32_t t = __builtin_amdgcn_readfirstlane(s_task[it]);
-    const uint32_t must_wait = __builtin_amdgcn_readfirstlane(s_wait[it]);
-    if (t >= n_tasks) break;
+    if (t == kNone) break;
+    uint32_t pending = 0;
+    if (tid == 0) pending = issue();
+    auto hook = [&]() {
+      if (tid == 0) s_task[it ^ 1u] = finish(pending);
+    };
     const PTask tk = tasks[t];
     const PJob &jb = jobs[tk.job];
+    // wait for the job's pre tasks unless this workgroup has acquired them
+    // already (the strict mode acquires for every task): the job of the
+    // previous dependent task is known in every wave, others are looked up in
+    // the bitmap, which changes only after the wait's barrier, so the decision
+    // is the same in all waves
+    bool must_wait = false;
+    if (tk.kind & PT_WAIT) {
+      if (strict & 1u) must_wait = true;
+      else if (tk.job != ready_job)
+        must_wait = tk.job >= 2048 || !((s_ready[tk.job >> 5] >> (tk.job & 31)) & 1u);
+      ready_job = tk.job;
+    }
     if (must_wait) {
       if (tid == 0) {
         // every waiting workgroup polls the same counter, so back off (up to
@@ -305,9 +304,12 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (tk.job < 2048) s_ready[tk.job >> 5] |= 1u << (tk.job & 31);
       }
       __syncthreads();
+      // every wave read the bitmap for this task before the barrier above: the
+      // bit is set only now, so all waves took the same branch (the next read
+      // follows the next loop-top barrier)
+      if (tid == 0 && tk.job < 2048) s_ready[tk.job >> 5] |= 1u << (tk.job & 31);
       if (strict & 1u) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     const int logn = (int)jb.logN;
@@ -318,16 +320,24 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     const int tid_g = tid & ((1 << logt) - 1);
     const int words = (1 << logn) + (1 << (logn - kLdsPadShift));
     typename A::V *lds_g = lds + (size_t)group * words;
+    // (every path calls the hook once: a degree not compiled in runs nothing)
     if constexpr (LOGN_MIN == LOGN_MAX) {
-      run_task<A, LOGN_MIN, LOGE>(tk, jb, tid_g, group, lds_g);
+      run_task<A, LOGN_MIN, LOGE>(tk, jb, tid_g, group, lds_g, hook);
     } else {
       switch (logn) {
-        case 10: if constexpr (LOGN_MIN <= 10) run_task<A, 10, LOGE>(tk, jb, tid_g, group, lds_g); break;
-        case 11: if constexpr (LOGN_MIN <= 11) run_task<A, 11, LOGE>(tk, jb, tid_g, group, lds_g); break;
-        case 12: run_task<A, 12, LOGE>(tk, jb, tid_g, group, lds_g); break;
-        case 13: run_task<A, 13, LOGE>(tk, jb, tid_g, group, lds_g); break;
+        case 10:
+          if constexpr (LOGN_MIN <= 10) run_task<A, 10, LOGE>(tk, jb, tid_g, group, lds_g, hook);
+          else hook();
+          break;
+        case 11:
+          if constexpr (LOGN_MIN <= 11) run_task<A, 11, LOGE>(tk, jb, tid_g, group, lds_g, hook);
+          else hook();
+          break;
+        case 12: run_task<A, 12, LOGE>(tk, jb, tid_g, group, lds_g, hook); break;
+        case 13: run_task<A, 13, LOGE>(tk, jb, tid_g, group, lds_g, hook); break;
         default:
-          if constexpr (LOGN_MAX >= 14) run_task<A, 14, LOGE>(tk, jb, tid_g, group, lds_g);
+          if constexpr (LOGN_MAX >= 14) run_task<A, 14, LOGE>(tk, jb, tid_g, group, lds_g, hook);
+          else hook();
           break;
       }
     }
