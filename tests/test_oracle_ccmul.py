@@ -169,9 +169,11 @@ def test_mask_product_completes_the_online_protocol():
             assert np.array_equal(packing.conv_extract(d, geo), plain.mod_t(plain.conv2d(x[b], w[m:m + 1], P)[0], T))
 
 
-def test_noise_at_the_benchmark_ring():
+@pytest.mark.parametrize("bits", [48, 50])
+def test_noise_at_the_benchmark_ring(bits):
+    # the benchmark ring with the default primes below 2^48, and with 50-bit primes
     N, L = 8192, 3
-    q, psi, g, s = _keys(N, L, 50, 75)
+    q, psi, g, s = _keys(N, L, bits, 75)
     rlk, _, _ = _rlk(s, q, psi, g)
     ma, mb = g.integers(0, T, size=N), g.integers(0, T, size=N)
     A, B = _enc(ma, s, q, psi, g, N), _enc(mb, s, q, psi, g, N)
