@@ -262,3 +262,39 @@ def test_batched_weight_gradient_full_size(gpu_lib, ctxs):
         assert_equal_u64(he.to_numpy_u64(out), expect, "batched dW rep %d" % rep)
         assert_equal_u64(he.to_numpy_u64(conv["out"]), oracle_out(conv), "conv beside dW rep %d" % rep)
     he.he_batch_destroy(b)
+
+
+@pytest.mark.gpu
+def test_strict_sync_batch_of_long_and_short_sums(gpu_lib, ctxs):
+    # the strict mode (a fence at every dependency, for checking) gives the same
+    # bytes: a 64-term weight gradient accumulated onto its output next to conv
+    # jobs, two replays
+    he = gpu_lib
+    ctx = ctxs[(8192, 3)]
+    N, L, B, C, M, H, h, P = 8192, 3, 32, 16, 16, 16, 3, 1
+    plan = he.Plan(ctx, he.HE_KIND_DW, B=B, C=C, M=M, H=H, W=H, h=h, P=P)
+    cb = plan.info["cb"]
+    ct = synth.uniform_residues(synth.rng(3, synth.STREAM_CT, 21), (B * (cb + M), 2), ctx.q, N)
+    ptv = synth.uniform_mod_t(synth.rng(3, synth.STREAM_MASK, 21), (B * (M + cb), N))
+    row, cti, pti = packing.dw_terms(B, M, cb)
+    expect = core.csr_cpmul(ct, core.lift(ptv, ctx.q), row, cti, pti, ctx.q, ctx.psi, method=2)
+    out = he.empty_u64((plan.info["n_ct_out"], 2, L, N))
+    base = synth.uniform_residues(synth.rng(3, synth.STREAM_A, 23), (plan.info["n_ct_out"], 2), ctx.q, N)
+    q = np.array(ctx.q, dtype=np.uint64).reshape(1, 1, -1, 1)
+    convs = [make_job(he, ctxs, 0, 1, 470 + k) for k in range(2)]
+    b = he.he_batch_create(0)
+    he.he_batch_add(b, convs[0]["ctx"].h, convs[0]["plan"].h, convs[0]["d_ct"], convs[0]["d_w"], convs[0]["out"], 0)
+    he.he_batch_add(b, ctx.h, plan.h, he.to_device_u64(ct), torch.from_numpy(ptv).cuda(), out,
+                    he.HE_PLAIN_POLY | he.HE_ACCUMULATE)
+    he.he_batch_add(b, convs[1]["ctx"].h, convs[1]["plan"].h, convs[1]["d_ct"], convs[1]["d_w"], convs[1]["out"], 0)
+    he.he_batch_build(b, he.HE_BATCH_GRAPH | he.HE_BATCH_STRICT_SYNC)
+    print("case strict sync batch", flush=True)
+    for rep in range(2):
+        out.copy_(he.to_device_u64(base))
+        torch.cuda.synchronize()
+        he.he_batch_run(b)
+        he.he_batch_sync(b)
+        assert_equal_u64(he.to_numpy_u64(out), (base + expect) % q, "dW accumulated, strict, rep %d" % rep)
+        for k, c in enumerate(convs):
+            assert_equal_u64(he.to_numpy_u64(c["out"]), oracle_out(c), "conv %d strict rep %d" % (k, rep))
+    he.he_batch_destroy(b)
