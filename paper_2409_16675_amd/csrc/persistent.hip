@@ -15,11 +15,14 @@
 // coefficients whatever the degree, so the register budget does not depend on N.
 //
 // A multiply-accumulate task of job j waits until every pre task of job j has
-// finished (per-job counter, release/acquire at agent scope).  Because every
-// pre task precedes every multiply-accumulate task in the table, and a
-// workgroup takes no dependent task before the pre queue is empty, a waiting
-// task only waits on tasks already taken by running workgroups, so the wait
-// always ends; it is also bounded by a spin limit that raises an error flag.
+// finished: pre tasks write their outputs with device-coherent stores, wait for
+// them, and count themselves done in a per-job counter; the waiting workgroup
+// acquires the job once (an L2 invalidate).  Every pre task precedes every
+// multiply-accumulate task in the table and a workgroup's claims move forward
+// through the queues only, so no workgroup waits while holding a pre task: a
+// waiting task only waits on tasks that running workgroups will finish, and
+// the wait always ends; it is also bounded by a spin limit that raises an
+// error flag.
 #include "batch.hpp"
 #include "ntt.hpp"
 #include "mac.hpp"
