@@ -68,9 +68,9 @@ def kernel_src_sha(d=None):
 # digest of the sources the counters were taken on.
 TRAFFIC = {
     # (source digest, layer jobs per launch): bytes per launch, with the counter readings
-    ("61d3d305e75e3601", 10): {"bytes": 1299895153, "fetch_kib": 96226.4, "fetch_scale": 1.9999,
-                               "write_kib": 1076987.5, "write_scale": 1.0000,
-                               "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x10_hbm_bytes.md"},
+    ("61d3d305e75e3601", 20): {"bytes": 2550607432, "fetch_kib": 169053.2, "fetch_scale": 1.9999,
+                               "write_kib": 2152741.0, "write_scale": 1.0000,
+                               "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x20_hbm_bytes.md"},
     ("61d3d305e75e3601", 16): {"bytes": 2043834745, "fetch_kib": 136770.9, "fetch_scale": 1.9999,
                                "write_kib": 1722407.1, "write_scale": 1.0000,
                                "summary": "profiles/k_persistent_conv2d_fwd_b16_n8192_L3_x16_hbm_bytes.md"},
@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1024)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--jobs-per-launch", type=int, default=16,
-                    help="layer jobs (steps) the batched path runs per persistent launch")
+                    help="preferred layer jobs (steps) per persistent launch of the batched path (see launch_sizes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-legs", action="store_true",
@@ -161,10 +161,17 @@ def time_path(he, torch, wl, flags, steps, warmup, profile=False, preheat_ms=0.0
     return (t1 - t0) / steps, stats, out
 
 
+MOST_JOBS_PER_LAUNCH = 24
+
+
 def launch_sizes(steps, per_launch):
-    """The fewest launches of at most `per_launch` jobs covering `steps` steps,
-    their sizes differing by at most one (20 steps at 16: two launches of 10)."""
-    n = max(1, -(-steps // max(1, per_launch)))
+    """Launches covering `steps` steps, their sizes within one of each other: as
+    many as steps / per_launch rounds to (at least one), and more only where a
+    launch would exceed MOST_JOBS_PER_LAUNCH jobs (at 16 per launch: 20 steps
+    run as one launch of 20, 64 as four of 16).  Per job the persistent kernel
+    is fastest near 16 jobs a launch and slower both well below and well above
+    (one box: 48.9 / 47.3 / 46.4 / 45.9 / 47.0 us per job at 8 / 10 / 12 / 16 / 20)."""
+    n = max(1, int(steps / max(1, per_launch) + 0.5), -(-steps // MOST_JOBS_PER_LAUNCH))
     base, extra = divmod(steps, n)
     return [base + 1] * extra + [base] * (n - extra)
 
@@ -203,8 +210,7 @@ def preheat(he, b, stream, warmup, min_ms):
 
 def time_batched(he, torch, wl, steps, warmup, per_launch, preheat_ms):
     """The persistent fused kernel, replayed from a HIP graph, over exactly
-    `steps` layer jobs (steps) split into the fewest launches of at most
-    `per_launch` jobs, sizes within one of each other.  Returns seconds per
+    `steps` layer jobs (steps) split into launches by launch_sizes.  Returns seconds per
     step, the kernel's average duration per full-size launch, the outputs of
     the first launch's jobs, the batch and its info."""
     ctx, plan = wl["ctx"], wl["plan"]
@@ -669,7 +675,9 @@ def main():
         return 2
     import torch
     from paper_2409_16675_amd import he, synth
-    wl = workload(he, synth, torch, n_layers=args.jobs_per_launch)
+    # as many distinct layers as the largest launch holds jobs: no two jobs of a
+    # launch share inputs
+    wl = workload(he, synth, torch, n_layers=max(launch_sizes(args.steps, args.jobs_per_launch)))
     n_cpmul = wl["info"]["n_terms"]
     tune = he.he_autotune(wl["ctx"].h, 512)      # set-up: picks the fastest bit-exact schedules
     chosen = {name: he.he_ctx_get_schedule(wl["ctx"].h, op) for name, op in
@@ -697,7 +705,7 @@ def main():
         "metric": METRIC, "value": round(n_cpmul / dt, 1), "unit": "CPMul-acc/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
-        "path": "batched (persistent fused kernel, graph replay, up to %d layer jobs per launch)" % args.jobs_per_launch,
+        "path": "batched (persistent fused kernel, graph replay, launches of about %d layer jobs)" % args.jobs_per_launch,
         "jobs_per_launch": args.jobs_per_launch, "launch_sizes": binfo["launch_sizes"],
         "preheat": {"launches": binfo["preheat_launches"], "min_ms": args.preheat_ms,
                     "what": "untimed launches of the batch before the timed region (at least --warmup, then until "
