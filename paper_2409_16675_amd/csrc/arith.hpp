@@ -85,6 +85,20 @@ struct ArF64 {
     r = r < 0.0 ? r + q : r;
     return __builtin_bit_cast(uint64_t, r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
   }
+  // Bound (in units of q) under which store_out applies: the inverse
+  // transform's planner keeps its last stage's products below it.
+  static constexpr double kStoreIn = 0.99;
+  // canonical residue of an inverse transform's output x, |x| < q: floor(x / q)
+  // is -1 or 0, and one FMA gives x/q - 1/2 to within 2^-53 (fl(1/q) is within
+  // 2^-53 relative, then one rounding), while for integers 0 < |x| < q it is at
+  // least 2^-48 away from the ties -1/2 and -3/2 (x = 0 gives -1/2 exactly,
+  // which rint takes to -0): so rint finds floor(x / q) and the second FMA adds
+  // q back, exactly, when x < 0
+  __device__ __forceinline__ uint64_t store_out(V x) const {
+    const double t = __builtin_rint(__builtin_fma(x, qinv, -0.5));
+    const double r = __builtin_fma(-t, q, x);
+    return __builtin_bit_cast(uint64_t, r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+  }
   __device__ __forceinline__ V mul(V y, double w, double wq) const {
     double h = y * w;
     double l = __builtin_fma(y, w, -h);
@@ -132,6 +146,9 @@ struct ArU64 {
     x = x >= two_q ? x - two_q : x;
     return x >= q ? x - q : x;
   }
+  // an inverse transform's outputs are Shoup products in [0, 2q): the full store
+  static constexpr double kStoreIn = 1e9;
+  __device__ __forceinline__ uint64_t store_out(V x) const { return store(x); }
   // Shoup: y*w mod q in [0, 2q) for any y < 2^64
   __device__ __forceinline__ V mul(V y, uint64_t w, uint64_t ws) const {
     uint64_t Q = mulhi64(y, ws);

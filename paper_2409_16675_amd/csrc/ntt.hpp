@@ -228,8 +228,9 @@ constexpr PassPlan plan_gs(int R, double b_in) {
 // bits are zero while the product side stays below mul_out, so only the
 // growing slots are reduced (before a stage whose sum would leave the limit,
 // and at the end of the pass when above end_red).  In the last pass (LAST,
-// stages down to 0) stage 0 multiplies both outputs (N^-1 folded in), and no
-// slot is reduced at the end: the canonical store reduces every value.
+// stages down to 0) stage 0 multiplies both outputs (N^-1 folded in), its
+// sums are kept small enough that both products stay below kStoreIn (so the
+// store needs no reduction, see store_out), and no slot is reduced at the end.
 struct GsPlan {
   uint32_t red[6];   // red[uu]: slots reduced before stage uu; red[R]: slots reduced at the end
   double b_out;
@@ -247,11 +248,12 @@ constexpr GsPlan plan_gs_slots(int R, double b_in, bool last, double end_red) {
       if (p & (1 << uu)) continue;
       const int p2 = p | (1 << uu);
       double s = b[p] + b[p2];
-      if (s > A::kLimit || A::mul_out(s) > A::kLimit) {
+      const bool final_stage = last && uu == R - 1;
+      if (s > A::kLimit || A::mul_out(s) > A::kLimit || (final_stage && A::mul_out(s) > A::kStoreIn)) {
         m |= (1u << p) | (1u << p2);
         s = 2.0 * A::kReduced;
       }
-      b[p] = (last && uu == R - 1) ? A::mul_out(s) : s;
+      b[p] = final_stage ? A::mul_out(s) : s;
       b[p2] = A::mul_out(s);
     }
     pl.red[uu] = m;
@@ -688,7 +690,11 @@ __device__ __forceinline__ void ntt_inverse_regs(const A &ar, TwP tw, int tid, t
   }
   xchg_sync<G, 1, 0>();
   if constexpr (!PF) last.load(tw, tid);
-  auto st_out = [&](int t, int c, V x) { st(t + c, ar.store(x)); };
+  constexpr double end_red = inv_end_red<A, G>(B0X100 / 100.0);
+  static_assert(plan_gs_slots<A>(G::r(0), inv_bound_in<A, G>(0, B0X100 / 100.0, end_red), true, end_red).b_out <=
+                    A::kStoreIn,
+                "the last stage's products exceed the bound store_out needs");
+  auto st_out = [&](int t, int c, V x) { st(t + c, ar.store_out(x)); };
   inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
 }
 

@@ -3,7 +3,9 @@ lazy reduction) on the CPU, instruction by instruction in IEEE double
 precision: every product is congruent to the exact product mod q, and its
 magnitude stays within the bounds the compile-time reduction planner and the
 multiply-accumulate rely on (mul_out, mulv_out, the reduced bound 0.51 q and
-the 31 q limit), at worst-case operands for primes just below 2^48.
+the 31 q limit), at worst-case operands for primes just below 2^48; and the
+store of the inverse transform's outputs (|x| < q, no reduction) yields the
+canonical residue.
 
 Python floats are IEEE binary64 with correctly rounded * and +, round() ties
 to even like rint, and a fused multiply-add is formed exactly with rationals
@@ -44,6 +46,12 @@ def mul(q, y, w, wq):
 
 def reduce(q, qinv, x):
     return fma(-rint(x * qinv), q, x)
+
+
+def store_out(q, qinv, x):
+    # floor(x / q) in {-1, 0} from one estimate, then q added back when negative
+    t = rint(fma(x, qinv, -0.5))
+    return fma(-t, q, x)
 
 
 def operands(q, bound, rng, n):
@@ -107,6 +115,21 @@ def test_reduce_and_accumulated_chunk(q):
     assert acc == int(acc) and abs(acc) <= worst
 
 
+@pytest.mark.parametrize("q", PRIMES)
+def test_store_of_outputs_below_q(q):
+    # the planner keeps the last stage's products below 0.99 q; every integer
+    # |x| < q, the edges included, reaches its canonical residue exactly
+    rng = random.Random(q + 3)
+    qf, qinv = float(q), 1.0 / float(q)
+    assert mul_out(0.48 / 0.0625) <= 0.99 + 1e-12 < 1.0
+    h = q // 2
+    xs = [0, 1, -1, 2, -2, q - 1, -(q - 1), q - 2, -(q - 2), h, -h, h + 1, -(h + 1), h - 1, -(h - 1)]
+    xs += [rng.randrange(-q + 1, q) for _ in range(4000)]
+    for x in xs:
+        r = store_out(qf, qinv, float(x))
+        assert r == int(r) and int(r) == x % q, (x, r)
+
+
 def test_bounds_used_by_the_kernels_are_the_ones_checked():
     # the constants the device policy declares (arith.hpp) equal the ones above
     import os
@@ -116,3 +139,7 @@ def test_bounds_used_by_the_kernels_are_the_ones_checked():
     assert re.search(r"kLimit = 31\.0;", f64) and re.search(r"kReduced = 0\.51;", f64)
     assert "mul_out(double b_in) { return 0.5 + 0.0625 * b_in + 0.01; }" in f64
     assert "mulv_out(double b_in) { return 0.5 + 0.09375 * b_in + 0.01; }" in f64
+    assert re.search(r"kStoreIn = 0\.99;", f64)
+    body = f64[f64.index("uint64_t store_out(V x) const {"):]
+    body = body[:body.index("}")]
+    assert "__builtin_rint(__builtin_fma(x, qinv, -0.5))" in body and "__builtin_fma(-t, q, x)" in body
