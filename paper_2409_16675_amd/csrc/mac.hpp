@@ -159,7 +159,7 @@ __device__ __forceinline__ void mac_terms_ws(const ArF64 &ar, double (&acc)[E], 
       }
     }
   };
-  if (t0 >= t1) {
+  if (__builtin_expect(t0 >= t1, 0)) {
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j] = 0.0;
     return;

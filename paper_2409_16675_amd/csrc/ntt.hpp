@@ -21,6 +21,7 @@
 // exchange through LDS (the last forward pass stores directly only for runs
 // of at most 4, see ntt_forward_tc).
 #pragma once
+#include <type_traits>
 #include "arith.hpp"
 
 namespace he {
@@ -118,6 +119,35 @@ __device__ __forceinline__ Tw load_tw(const HE_GLOBAL Tw *tw, uint32_t idx) {
   static_assert(sizeof(Tw) == sizeof(u64x2), "twiddle entries are 16 bytes");
   const u64x2 v = *(const HE_GLOBAL u64x2 *)((const HE_GLOBAL char *)tw + (size_t)(idx * (uint32_t)sizeof(Tw)));
   return __builtin_bit_cast(Tw, v);
+}
+
+// Raw buffer access: the resource holds a base address and a bound of
+// `bytes`; an access adds a per-lane byte offset (a VGPR) and a scalar one (an
+// SGPR or constant), so an index's compile-time part costs no vector address
+// arithmetic.  The base must be the same in every lane: it is read from the
+// first lane, so that the compiler, which cannot always prove it uniform, does
+// not wrap each access in a loop over distinct bases.  Word 3 selects raw
+// 32-bit data (gfx950).  Offsets stay below the bound here; past it the
+// hardware would read zeros and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes) {
+  const uint64_t a = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void *u = (void *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, (int)bytes, 0x00020000);
+}
+template <class Tw>
+__device__ __forceinline__ Tw load_tw_buf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  static_assert(sizeof(Tw) == 16, "twiddle entries are 16 bytes");
+  return __builtin_bit_cast(Tw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0));
+}
+typedef unsigned int he_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint64_t buf_load_u64(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+// a streaming store (nt: the line is not kept for reuse)
+__device__ __forceinline__ void buf_store_u64_nt(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, uint64_t x) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(he_u32x2, x), rs, (int)voff, (int)soff, 2);
 }
 
 // One twiddle entry at an index that every lane of the wave shares: the table
@@ -412,12 +442,21 @@ struct PassTw {
           for (int j = 0; j < (1 << u); ++j)
             w[g][(1 << u) - 1 + j] = load_tw_uniform<Tw>(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
       } else {
-        const uint32_t high = (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(tid, g, 0) >> (NLOW + R);
+        // entries differ across the lanes: the thread's part of the index
+        // (shifted per stage) is the lane offset, the compile-time part (stage,
+        // group, entry) the scalar offset of a buffer load, so the addresses
+        // cost no per-entry vector arithmetic (the two parts have disjoint
+        // bits, see pass_index)
+        const auto rs = buf_rsrc((const void *)tw, (uint32_t)(G::N * sizeof(Tw)));
+        const uint32_t high_t = (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0) >> (NLOW + R);
 #pragma unroll
-        for (int u = 0; u < R; ++u)
+        for (int u = 0; u < R; ++u) {
+          const uint32_t vo = (high_t << u) * (uint32_t)sizeof(Tw);
 #pragma unroll
           for (int j = 0; j < (1 << u); ++j)
-            w[g][(1 << u) - 1 + j] = load_tw(tw, (1u << (S0 + u)) + (high << u) + (uint32_t)j);
+            w[g][(1 << u) - 1 + j] =
+                load_tw_buf<Tw>(rs, vo, ((1u << (S0 + u)) + (high_g << u) + (uint32_t)j) * (uint32_t)sizeof(Tw));
+        }
       }
     }
     if constexpr (INV && S0 == 0) {
@@ -694,7 +733,12 @@ __device__ __forceinline__ void ntt_inverse_regs(const A &ar, TwP tw, int tid, t
   static_assert(plan_gs_slots<A>(G::r(0), inv_bound_in<A, G>(0, B0X100 / 100.0, end_red), true, end_red).b_out <=
                     A::kStoreIn,
                 "the last stage's products exceed the bound store_out needs");
-  auto st_out = [&](int t, int c, V x) { st(t + c, ar.store_out(x)); };
+  // (a store taking the index's two parts, thread and compile-time, can
+  // address with a lane offset and a scalar one)
+  auto st_out = [&](int t, int c, V x) {
+    if constexpr (std::is_invocable_v<St &, int, int, uint64_t>) st(t, c, ar.store_out(x));
+    else st(t + c, ar.store_out(x));
+  };
   inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
 }
 

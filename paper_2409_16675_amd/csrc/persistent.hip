@@ -189,8 +189,10 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       ntt_inverse_regs<A, G, kMacOut, false>(ar, twi, tid_g, lds_g, first, v, st);
     } else {
       // streaming stores: output planes are not read again by this launch
-      auto st = [&](int k, uint64_t x) {
-        if (valid) __builtin_nontemporal_store(x, &dst[(uint32_t)k]);
+      // (addressed as the thread's part plus a compile-time part; the resource
+      // is formed at the stores, not held across the transform)
+      auto st = [&](int t, int c, uint64_t x) {
+        if (valid) buf_store_u64_nt(buf_rsrc((const void *)dst, G::N * 8u), (uint32_t)t * 8u, (uint32_t)c * 8u, x);
       };
       ntt_inverse_regs<A, G, kMacOut, false>(ar, twi, tid_g, lds_g, first, v, st);
     }
