@@ -85,19 +85,30 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   constexpr bool kF64 = std::is_same<A, ArF64>::value;
   if (kind == PT_FWD_CT) {
     hook();
-    const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)plane * G::N;
+    // (a member past the task's planes transforms the task's first plane,
+    // always a valid input, and stores nothing: no per-coefficient selects)
+    const HE_GLOBAL uint64_t *src = as_global(jb.ct_in) + (size_t)(valid ? plane : tk.first) * G::N;
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_hat) + (size_t)plane * G::N;
-    auto ld = [&](int k) { return ar.load(valid ? src[(uint32_t)k] : 0ull); };
-    // (inputs kept for later jobs are stored as canonical residues: ct_f64 = 0)
-    const bool as_f64 = kF64 && jb.ct_f64;
-    auto st = [&](int k, V v) {
-      if constexpr (kF64) {
-        if (valid) publish(dst + (uint32_t)k, as_f64 ? __builtin_bit_cast(uint64_t, ar.reduce(v)) : ar.store(v));
-      } else {
-        if (valid) publish(dst + (uint32_t)k, ar.store(v));
-      }
+    auto ld = [&](int k) { return ar.load(src[(uint32_t)k]); };
+    // the output format is uniform over the task (inputs kept for later jobs
+    // are stored as canonical residues: ct_f64 = 0), so each format has its own
+    // transform and the stores carry no per-coefficient branch on it
+    auto run = [&](auto f64_out) {
+      auto st = [&](int k, V v) {
+        if constexpr (decltype(f64_out)::value) {
+          if (valid) publish(dst + (uint32_t)k, __builtin_bit_cast(uint64_t, ar.reduce(v)));
+        } else {
+          if (valid) publish(dst + (uint32_t)k, ar.store(v));
+        }
+      };
+      ntt_forward<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     };
-    ntt_forward<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
+    if constexpr (kF64) {
+      if (jb.ct_f64) run(std::true_type{});
+      else run(std::false_type{});
+    } else {
+      run(std::false_type{});
+    }
   } else if (kind == PT_PT) {
     hook();
     const uint32_t pp = valid ? plane / L : 0;
@@ -111,7 +122,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     };
     if (jb.pkind == PK_POLY) {
       const HE_GLOBAL int64_t *src = as_global((const int64_t *)jb.plain) + (size_t)pp * G::N;
-      auto ld = [&](int k) { return ar.load_signed(valid ? src[(uint32_t)k] : 0ll); };
+      auto ld = [&](int k) { return ar.load_signed(src[(uint32_t)k]); };   // (pp = 0 past the planes: a valid row)
       ntt_forward<A, G, true, false, true>(ar, PTw<A>::fwd(jb) + (size_t)i * G::N, tid_g, lds_g, ld, st);
     } else {
       // pack in LDS: zero, scatter this polynomial's weights, then transform from LDS
