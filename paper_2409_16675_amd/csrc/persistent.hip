@@ -56,6 +56,24 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Record idx of a table that no kernel writes during the launch, at an index
+// that is the same in every lane: read through the constant address space as
+// 32-byte words (records are copied out as vectors, then cast back), so the
+// compiler uses scalar loads.
+template <class T>
+__device__ __forceinline__ T load_const(const T *p, uint32_t idx) {
+  typedef uint32_t w8 __attribute__((ext_vector_type(8)));
+  static_assert(sizeof(T) % sizeof(w8) == 0, "records of whole 32-byte words");
+  constexpr int n = sizeof(T) / sizeof(w8);
+  const HE_CONST w8 *c = (const HE_CONST w8 *)(uintptr_t)p + (size_t)idx * n;
+  struct Words {
+    w8 v[n];
+  } r;
+#pragma unroll
+  for (int k = 0; k < n; ++k) r.v[k] = c[k];
+  return __builtin_bit_cast(T, r);
+}
+
 template <class A>
 struct PTw {
   using T = typename A::Tw;
@@ -75,7 +93,8 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
   const bool valid = plane < tk.first + tk.count;
   const uint32_t L = jb.L;
   const uint32_t i = valid ? plane % L : 0;
-  const PrimeK pk = jb.primes[i];
+  // (a plane group holds whole waves: the prime index is the same in every lane of a wave)
+  const PrimeK pk = load_const(jb.primes, __builtin_amdgcn_readfirstlane(i));
   const A ar(pk);
   const uint32_t kind = tk.kind & PT_KIND_MASK;
   // The batch's own transformed operands (inputs and plaintexts) stay in the
@@ -291,7 +310,7 @@ __global__ __launch_bounds__((PCfg<A, SLAB, LOGE, LOGN_MIN, LOGN_MAX>::NT),
     auto hook = [&]() {
       if (tid == 0) s_task[it ^ 1u] = finish(pending);
     };
-    const PTask tk = tasks[t];
+    const PTask tk = load_const(tasks, t);
     const PJob &jb = jobs[tk.job];
     // wait for the job's pre tasks unless this workgroup has acquired them
     // already (the strict mode acquires for every task): the job of the
