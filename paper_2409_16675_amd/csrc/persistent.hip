@@ -74,6 +74,10 @@ __device__ __forceinline__ T load_const(const T *p, uint32_t idx) {
   return __builtin_bit_cast(T, r);
 }
 
+// An int32 table that no kernel writes during the launch, read at indices the
+// same in every lane (scalar loads).
+#define CONST_I32(p) ((const HE_CONST int32_t *)(uintptr_t)(p))
+
 template <class A>
 struct PTw {
   using T = typename A::Tw;
@@ -167,10 +171,11 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       t0 = tk.t0;
       t1 = tk.t1;
     } else if (valid) {
-      t0 = as_global(jb.row)[o];
-      t1 = as_global(jb.row)[o + 1];
+      t0 = CONST_I32(jb.row)[o];
+      t1 = CONST_I32(jb.row)[o + 1];
     }
-    const HE_GLOBAL int32_t *cti = as_global(jb.cti), *pti = as_global(jb.pti);
+    // (term lists: indices the same in every lane, read with scalar loads)
+    const HE_CONST int32_t *cti = CONST_I32(jb.cti), *pti = CONST_I32(jb.pti);
     const HE_GLOBAL uint64_t *ct_hat = as_global((const uint64_t *)jb.ct_hat), *pt_hat = as_global((const uint64_t *)jb.pt_hat);
     auto planes = [&](int t) {
       if (listed && t == t0) return std::pair<uint32_t, uint32_t>(tk.a0, tk.b0);
