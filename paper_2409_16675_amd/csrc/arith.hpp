@@ -107,7 +107,8 @@ struct ArF64 {
     return r + l;
   }
   __device__ __forceinline__ V mul(V y, Tw w) const { return mul(y, w.w, w.wq); }
-  // product of two residues with |a| <= q, 0 <= b < q (b's quotient companion formed here)
+  // product of |a| <= kLimit q and a canonical 0 <= b < q (b's quotient
+  // companion formed here; bound mulv_out)
   __device__ __forceinline__ V mulv(V a, V b) const { return mul(a, b, b * qinv); }
   __device__ __forceinline__ void ct(V &x, V &y, Tw w) const {
     V t = mul(y, w);
@@ -130,6 +131,7 @@ struct ArU64 {
   static constexpr double kCanon = 1.0;
   static constexpr double kReduced = 1.0;
   static constexpr double mul_out(double) { return 1.0; }
+  static constexpr double mulv_out(double) { return 1.0; }   // (no companions formed in this policy)
 
   __device__ __forceinline__ explicit ArU64(const PrimeK &p) : q(p.q), two_q(p.two_q) {}
 

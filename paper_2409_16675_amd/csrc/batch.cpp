@@ -80,6 +80,7 @@ static he_status fill_job(const JobRef &bj, char *ws, int arith, PJob &pj) {
   pj.primes = c.d_primes;
   pj.tw_fwd = arith == HE_ARITH_F64 ? c.d_tw_f64_fwd : c.d_tw_u64_fwd;
   pj.tw_inv = arith == HE_ARITH_F64 ? c.d_tw_f64_inv : c.d_tw_u64_inv;
+  pj.tw_inv_w = arith == HE_ARITH_F64 ? c.d_tw_f64_inv_w : nullptr;
   pj.ct_in = bj.job.ct_in;
   pj.ct_hat = (f & HE_IN_NTT) ? const_cast<uint64_t *>(bj.job.ct_in) : (uint64_t *)ws;
   pj.pt_hat = (uint64_t *)(ws + ct_hat_bytes(bj));

@@ -32,6 +32,7 @@ struct PTask {
 struct PJob {
   const PrimeK *primes;
   const void *tw_fwd, *tw_inv;
+  const double *tw_inv_w;   // fp64: the inverse twiddles alone, [L][N]
   const uint64_t *ct_in;
   uint64_t *ct_hat;      // == ct_in when the inputs are already transformed
   const void *plain;

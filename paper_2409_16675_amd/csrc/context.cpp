@@ -183,9 +183,15 @@ he_status build_context(const he_params *p, Ctx **out, uint32_t max_L) {
     return hip_fail(e, "hipSetDevice");
   }
   const size_t tb = (size_t)L * N * 16;
+  // the fp64 inverse table is followed by its twiddles alone (8 bytes each),
+  // for transform passes whose lanes read different entries: half the bytes
+  // and registers, the quotient companion formed at the product
+  std::vector<unsigned char> fiw(tb + (size_t)L * N * 8);
+  std::memcpy(fiw.data(), fi.data(), tb);
+  for (size_t j = 0; j < fi.size(); ++j) std::memcpy(fiw.data() + tb + j * 8, &fi[j].w, 8);
   void *mem[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  const size_t sz[5] = {sizeof(PrimeK) * L, tb, tb, tb, tb};
-  const void *src[5] = {pk.data(), ff.data(), fi.data(), uf.data(), ui.data()};
+  const size_t sz[5] = {sizeof(PrimeK) * L, tb, tb + (size_t)L * N * 8, tb, tb};
+  const void *src[5] = {pk.data(), ff.data(), fiw.data(), uf.data(), ui.data()};
   for (int j = 0; j < 5; ++j) {
     if ((e = hipMalloc(&mem[j], sz[j])) != hipSuccess || (e = hipMemcpy(mem[j], src[j], sz[j], hipMemcpyHostToDevice)) != hipSuccess) {
       for (int k = 0; k <= j; ++k)
@@ -197,6 +203,7 @@ he_status build_context(const he_params *p, Ctx **out, uint32_t max_L) {
   c->d_primes = (PrimeK *)mem[0];
   c->d_tw_f64_fwd = mem[1];
   c->d_tw_f64_inv = mem[2];
+  c->d_tw_f64_inv_w = (const double *)((const char *)mem[2] + tb);
   c->d_tw_u64_fwd = mem[3];
   c->d_tw_u64_inv = mem[4];
   *out = c;

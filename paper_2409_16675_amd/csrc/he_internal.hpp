@@ -29,7 +29,8 @@ struct Ctx {
   // device tables
   PrimeK *d_primes = nullptr;        // [L]
   void *d_tw_f64_fwd = nullptr;      // TwF64 [L][N]
-  void *d_tw_f64_inv = nullptr;
+  void *d_tw_f64_inv = nullptr;     // TwF64 [L][N], then the twiddles alone:
+  const double *d_tw_f64_inv_w = nullptr;   // double [L][N] (same allocation)
   void *d_tw_u64_fwd = nullptr;      // TwU64 [L][N]
   void *d_tw_u64_inv = nullptr;
   // per-kernel timing (he_ctx_profile)

@@ -267,8 +267,11 @@ struct GsPlan {
 };
 
 template <class A>
-constexpr GsPlan plan_gs_slots(int R, double b_in, bool last, double end_red) {
+constexpr GsPlan plan_gs_slots(int R, double b_in, bool last, double end_red, bool formed = false) {
   GsPlan pl{{0u, 0u, 0u, 0u, 0u, 0u}, b_in};
+  // (formed: the pass's twiddles come without their quotient companions,
+  // formed at the product, whose bound is then mulv_out)
+  auto pout = [formed](double x) { return formed ? A::mulv_out(x) : A::mul_out(x); };
   double b[32] = {};
   const int n = 1 << R;
   for (int p = 0; p < n; ++p) b[p] = b_in;
@@ -279,12 +282,12 @@ constexpr GsPlan plan_gs_slots(int R, double b_in, bool last, double end_red) {
       const int p2 = p | (1 << uu);
       double s = b[p] + b[p2];
       const bool final_stage = last && uu == R - 1;
-      if (s > A::kLimit || A::mul_out(s) > A::kLimit || (final_stage && A::mul_out(s) > A::kStoreIn)) {
+      if (s > A::kLimit || pout(s) > A::kLimit || (final_stage && pout(s) > A::kStoreIn)) {
         m |= (1u << p) | (1u << p2);
         s = 2.0 * A::kReduced;
       }
-      b[p] = final_stage ? A::mul_out(s) : s;
-      b[p2] = A::mul_out(s);
+      b[p] = final_stage ? pout(s) : s;
+      b[p2] = pout(s);
     }
     pl.red[uu] = m;
   }
@@ -310,22 +313,23 @@ constexpr double fwd_bound_in(int k) {
   return b;
 }
 // Inverse passes run k = NPASS-1 down to 0; the input is canonical (or a reduced accumulator).
-template <class A, class G>
+// WMASK: bit k set when pass k forms its twiddles' quotient companions.
+template <class A, class G, int WMASK = 0>
 constexpr double inv_bound_in(int k, double b0, double end_red) {
   double b = b0;
-  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs_slots<A>(G::r(j), b, j == 0, end_red).b_out;
+  for (int j = G::NPASS - 1; j > k; --j) b = plan_gs_slots<A>(G::r(j), b, j == 0, end_red, (WMASK >> j) & 1).b_out;
   return b;
 }
 // Reductions per thread over a whole inverse transform, and the end-of-pass
 // threshold (in units of q) that needs the fewest for this geometry and input
 // bound: a low threshold reduces more at pass ends, a high one more inside
 // the next pass.
-template <class A, class G>
+template <class A, class G, int WMASK = 0>
 constexpr int inv_reductions(double b0, double end_red) {
   int tot = 0;
   double b = b0;
   for (int j = G::NPASS - 1; j >= 0; --j) {
-    const GsPlan p = plan_gs_slots<A>(G::r(j), b, j == 0, end_red);
+    const GsPlan p = plan_gs_slots<A>(G::r(j), b, j == 0, end_red, (WMASK >> j) & 1);
     int c = 0;
     for (int u = 0; u <= G::r(j); ++u) c += __builtin_popcount(p.red[u]);
     tot += c * (G::E >> G::r(j));
@@ -333,13 +337,13 @@ constexpr int inv_reductions(double b0, double end_red) {
   }
   return tot;
 }
-template <class A, class G>
+template <class A, class G, int WMASK = 0>
 constexpr double inv_end_red(double b0) {
   constexpr double cands[] = {2.0, 2.5, 3.0, 3.5, 4.0};
   double best = cands[0];
-  int best_n = inv_reductions<A, G>(b0, cands[0]);
+  int best_n = inv_reductions<A, G, WMASK>(b0, cands[0]);
   for (double c : cands) {
-    const int n = inv_reductions<A, G>(b0, c);
+    const int n = inv_reductions<A, G, WMASK>(b0, c);
     if (n < best_n) {
       best_n = n;
       best = c;
@@ -386,6 +390,14 @@ __device__ __forceinline__ void gs_last<ArU64>(const ArU64 &ar, uint64_t &x, uin
   y = ar.mul(d, wn);
 }
 
+// The same with the twiddle alone (fp64): its quotient companion is formed
+// at the product (mulv), whose bound is mulv_out.
+__device__ __forceinline__ void gs_bfly_formed(const ArF64 &ar, double &x, double &y, double w) {
+  double d = x - y;
+  x = x + y;
+  y = ar.mulv(d, w);
+}
+
 template <class A>
 __device__ __forceinline__ typename A::V reduce_gs_in(const A &ar, typename A::V v) {
   return ar.reduce(v);
@@ -408,16 +420,45 @@ constexpr int thread_bits_above(int limit) {
   return m;
 }
 
-template <class A, class G, int K, bool INV>
+// W: the entries are the twiddles alone (8 bytes, from a table without the
+// quotient companions; only for passes whose lanes read different entries,
+// fp64): half the bytes and registers, the companion formed at the product.
+template <class A, class G, int K, bool INV, bool W = false>
 struct PassTw {
   static constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R, NLOW = G::LOGN - S0 - R;
-  typename A::Tw w[NG][(1 << R) - 1];
+  static constexpr bool kW = W;
+  std::conditional_t<W, double, typename A::Tw> w[NG][(1 << R) - 1];
   typename A::Tw n0, n1;
   // the index bits above the stage bits ("high") select a group's entries
   static constexpr bool kPlaneUniform = thread_bits_above<G, K>(G::LOGT) == 0;
   static constexpr bool kWaveUniform = thread_bits_above<G, K>(6) == 0;
+  static_assert(!W || (!kWaveUniform && std::is_same<A, ArF64>::value), "twiddles alone: per-lane fp64 passes only");
+  // the entries of this pass from the paired table tw, or from the table of
+  // twiddles alone tww when W
+  template <class TwP>
+  __device__ __forceinline__ void load2(TwP tw, const double *tww, int tid) {
+    if constexpr (W) {
+      const auto rs = buf_rsrc((const void *)tww, (uint32_t)(G::N * 8));
+      const uint32_t high_t = (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0) >> (NLOW + R);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const uint32_t high_g = (uint32_t)pass_index<G::LOGN, G::LOGT, S0, R>(0, g, 0) >> (NLOW + R);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const uint32_t vo = (high_t << u) * 8u;
+#pragma unroll
+          for (int j = 0; j < (1 << u); ++j)
+            w[g][(1 << u) - 1 + j] = __builtin_bit_cast(
+                double, buf_load_u64(rs, vo, ((1u << (S0 + u)) + (high_g << u) + (uint32_t)j) * 8u));
+        }
+      }
+    } else {
+      load(tw, tid);
+    }
+  }
   template <class TwP>
   __device__ __forceinline__ void load(TwP tw, int tid) {
+    static_assert(!W, "use load2");
     using Tw = typename A::Tw;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -515,13 +556,18 @@ __device__ __forceinline__ uint32_t slot_index(int tid, int e) {
 
 // Inverse pass K (stages S0+R-1 down to S0) on values already in registers
 // (slot e holds coefficient slot_index<G, K>(tid, e)).  B0 is the bound of the
-// transform's input.
-template <class A, class G, int K, int B0X100, class St, class Mid>
-__device__ __forceinline__ void inv_pass_v(const A &ar, const PassTw<A, G, K, true> &twr, int tid,
+// transform's input; WMASK bit k marks the passes with twiddles alone.
+template <int WMASK, int K>
+constexpr bool wbit() {
+  return ((WMASK >> K) & 1) != 0;
+}
+template <class A, class G, int K, int B0X100, int WMASK = 0, class St, class Mid>
+__device__ __forceinline__ void inv_pass_v(const A &ar, const PassTw<A, G, K, true, wbit<WMASK, K>()> &twr, int tid,
                                            typename A::V (&v)[G::E], St st, Mid mid) {
   constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
-  constexpr double end_red = inv_end_red<A, G>(B0X100 / 100.0);
-  constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G>(K, B0X100 / 100.0, end_red), K == 0, end_red);
+  constexpr double end_red = inv_end_red<A, G, WMASK>(B0X100 / 100.0);
+  constexpr GsPlan pp = plan_gs_slots<A>(R, inv_bound_in<A, G, WMASK>(K, B0X100 / 100.0, end_red), K == 0, end_red,
+                                         wbit<WMASK, K>());
   static_assert(pp.b_out <= A::kLimit + 1e-9, "fp64 bound exceeded");
   const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
 #pragma unroll
@@ -539,6 +585,8 @@ __device__ __forceinline__ void inv_pass_v(const A &ar, const PassTw<A, G, K, tr
         const int p2 = p | (1 << (R - 1 - u));
         if (s == 0) {
           gs_last<A>(ar, v[(g << R) | p], v[(g << R) | p2], twr.n0, twr.n1);
+        } else if constexpr (wbit<WMASK, K>()) {
+          gs_bfly_formed(ar, v[(g << R) | p], v[(g << R) | p2], twr.w[g][(1 << u) - 1 + (p >> (R - u))]);
         } else {
           gs_bfly<A>(ar, v[(g << R) | p], v[(g << R) | p2], twr.w[g][(1 << u) - 1 + (p >> (R - u))]);
         }
@@ -556,9 +604,9 @@ __device__ __forceinline__ void inv_pass_v(const A &ar, const PassTw<A, G, K, tr
 }
 
 // Inverse pass K reading its input through ld(t, c).
-template <class A, class G, int K, int B0X100, class Ld, class St, class Mid>
-__device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true> &twr, int tid, Ld ld, St st,
-                                         Mid mid) {
+template <class A, class G, int K, int B0X100, int WMASK = 0, class Ld, class St, class Mid>
+__device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true, wbit<WMASK, K>()> &twr, int tid, Ld ld,
+                                         St st, Mid mid) {
   constexpr int S0 = G::s0(K), R = G::r(K), NG = G::E >> R;
   const int t = pass_index<G::LOGN, G::LOGT, S0, R>(tid, 0, 0);
   typename A::V v[G::E];
@@ -566,7 +614,7 @@ __device__ __forceinline__ void inv_pass(const A &ar, const PassTw<A, G, K, true
   for (int g = 0; g < NG; ++g)
 #pragma unroll
     for (int p = 0; p < (1 << R); ++p) v[(g << R) | p] = ld(t, pass_index<G::LOGN, G::LOGT, S0, R>(0, g, p));
-  inv_pass_v<A, G, K, B0X100>(ar, twr, tid, v, st, mid);
+  inv_pass_v<A, G, K, B0X100, WMASK>(ar, twr, tid, v, st, mid);
 }
 
 // A pass loads and stores the same thread-private set of indices, so passes
@@ -631,20 +679,22 @@ __device__ __forceinline__ void fwd_lds_passes(const A &ar, TwP tw, int tid, typ
 }
 
 // Inverse passes K down to 1, LDS to LDS; `cur` holds pass K's twiddles and
-// `last` receives pass 0's (pass 0 is run by the caller, to HBM).
-template <class A, class G, int K, int B0X100, bool PF, class TwP>
-__device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, int tid, typename A::V *lds,
-                                               PassTw<A, G, K, true> &cur, PassTw<A, G, 0, true> &last) {
+// `last` receives pass 0's (pass 0 is run by the caller, to HBM).  tww: the
+// table of twiddles alone, for the passes WMASK marks.
+template <class A, class G, int K, int B0X100, bool PF, int WMASK, class TwP>
+__device__ __forceinline__ void inv_lds_passes(const A &ar, TwP tw, const double *tww, int tid, typename A::V *lds,
+                                               PassTw<A, G, K, true, wbit<WMASK, K>()> &cur,
+                                               PassTw<A, G, 0, true> &last) {
   xchg_sync<G, K + 1, K>();
-  if constexpr (!PF) cur.load(tw, tid);
+  if constexpr (!PF) cur.load2(tw, tww, tid);
   if constexpr (K > 1) {
-    PassTw<A, G, K - 1, true> nxt;
-    inv_pass<A, G, K, B0X100>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
-      if constexpr (PF) nxt.load(tw, tid);
+    PassTw<A, G, K - 1, true, wbit<WMASK, K - 1>()> nxt;
+    inv_pass<A, G, K, B0X100, WMASK>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
+      if constexpr (PF) nxt.load2(tw, tww, tid);
     });
-    inv_lds_passes<A, G, K - 1, B0X100, PF>(ar, tw, tid, lds, nxt, last);
+    inv_lds_passes<A, G, K - 1, B0X100, PF, WMASK>(ar, tw, tww, tid, lds, nxt, last);
   } else {
-    inv_pass<A, G, K, B0X100>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
+    inv_pass<A, G, K, B0X100, WMASK>(ar, cur, tid, LdsAt<typename A::V>{lds}, LdsPut<typename A::V>{lds}, [&] {
       if constexpr (PF) last.load(tw, tid);
     });
   }
@@ -703,34 +753,47 @@ __device__ __forceinline__ void ntt_forward(const A &ar, TwP tw, int tid, typena
   ntt_forward_tc<A, G, PF, CANON, LINEAR>(ar, tw, tid, lds, [&](int t, int c) { return ld(t + c); }, st);
 }
 
+// The inverse passes (above pass 0) whose lanes read different twiddle
+// entries: bit k for pass k, the passes that can take twiddles alone.
+template <class G, int K = 1>
+constexpr int lane_passes() {
+  if constexpr (K >= G::NPASS) {
+    return 0;
+  } else {
+    return (thread_bits_above<G, K>(6) != 0 ? (1 << K) : 0) | lane_passes<G, K + 1>();
+  }
+}
+
 // Whole inverse transform of values v already in registers in the layout of
 // its first pass (slot e holds coefficient slot_index<G, NPASS-1>(tid, e), bound
 // B0X100/100 q): that pass has no low index bits, so a producer reading or
 // computing the values pointwise fills it without a round trip through LDS.
 // Pass 0 writes st(i, canonical) in coalesced order.  `first` holds the first
-// pass's twiddles (loaded by the caller, ahead of the values).
-template <class A, class G, int B0X100, bool PF = true, class TwP, class St>
+// pass's twiddles (loaded by the caller, ahead of the values).  WMASK marks
+// the passes (never pass 0) whose twiddles come alone from tww.
+template <class A, class G, int B0X100, bool PF = true, int WMASK = 0, class TwP, class St>
 __device__ __forceinline__ void ntt_inverse_regs(const A &ar, TwP tw, int tid, typename A::V *lds,
-                                                 const PassTw<A, G, G::NPASS - 1, true> &first,
-                                                 typename A::V (&v)[G::E], St st) {
+                                                 const PassTw<A, G, G::NPASS - 1, true, wbit<WMASK, G::NPASS - 1>()> &first,
+                                                 typename A::V (&v)[G::E], St st, const double *tww = nullptr) {
   static_assert(G::NPASS >= 2, "at least two passes");
+  static_assert((WMASK & 1) == 0, "the last pass reads its twiddles with their companions");
   using V = typename A::V;
   PassTw<A, G, 0, true> last;
   if constexpr (G::NPASS > 2) {
-    PassTw<A, G, G::NPASS - 2, true> nxt;
-    inv_pass_v<A, G, G::NPASS - 1, B0X100>(ar, first, tid, v, LdsPut<V>{lds}, [&] {
-      if constexpr (PF) nxt.load(tw, tid);
+    PassTw<A, G, G::NPASS - 2, true, wbit<WMASK, G::NPASS - 2>()> nxt;
+    inv_pass_v<A, G, G::NPASS - 1, B0X100, WMASK>(ar, first, tid, v, LdsPut<V>{lds}, [&] {
+      if constexpr (PF) nxt.load2(tw, tww, tid);
     });
-    inv_lds_passes<A, G, G::NPASS - 2, B0X100, PF>(ar, tw, tid, lds, nxt, last);
+    inv_lds_passes<A, G, G::NPASS - 2, B0X100, PF, WMASK>(ar, tw, tww, tid, lds, nxt, last);
   } else {
-    inv_pass_v<A, G, 1, B0X100>(ar, first, tid, v, LdsPut<V>{lds}, [&] {
+    inv_pass_v<A, G, 1, B0X100, WMASK>(ar, first, tid, v, LdsPut<V>{lds}, [&] {
       if constexpr (PF) last.load(tw, tid);
     });
   }
   xchg_sync<G, 1, 0>();
   if constexpr (!PF) last.load(tw, tid);
-  constexpr double end_red = inv_end_red<A, G>(B0X100 / 100.0);
-  static_assert(plan_gs_slots<A>(G::r(0), inv_bound_in<A, G>(0, B0X100 / 100.0, end_red), true, end_red).b_out <=
+  constexpr double end_red = inv_end_red<A, G, WMASK>(B0X100 / 100.0);
+  static_assert(plan_gs_slots<A>(G::r(0), inv_bound_in<A, G, WMASK>(0, B0X100 / 100.0, end_red), true, end_red).b_out <=
                     A::kStoreIn,
                 "the last stage's products exceed the bound store_out needs");
   // (a store taking the index's two parts, thread and compile-time, can
@@ -739,7 +802,7 @@ __device__ __forceinline__ void ntt_inverse_regs(const A &ar, TwP tw, int tid, t
     if constexpr (std::is_invocable_v<St &, int, int, uint64_t>) st(t, c, ar.store_out(x));
     else st(t + c, ar.store_out(x));
   };
-  inv_pass<A, G, 0, B0X100>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
+  inv_pass<A, G, 0, B0X100, WMASK>(ar, last, tid, LdsAt<V>{lds}, st_out, [] {});
 }
 
 }  // namespace he

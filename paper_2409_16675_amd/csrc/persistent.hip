@@ -207,8 +207,12 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     // (the first pass's twiddles are loaded here, not with the operands: held
     // across the products they would push the kernel past its register budget)
     const auto twi = PTw<A>::inv(jb) + (size_t)i * G::N;
-    PassTw<A, G, G::NPASS - 1, true> first;
-    first.load(twi, tid_g);
+    // fp64: the passes whose lanes read different twiddles take them alone
+    // (8 bytes, the quotient companion formed at the product)
+    constexpr int kWM = kF64 ? lane_passes<G>() : 0;
+    const double *twi_w = kF64 ? jb.tw_inv_w + (size_t)i * G::N : nullptr;
+    PassTw<A, G, G::NPASS - 1, true, wbit<kWM, G::NPASS - 1>()> first;
+    first.load2(twi, twi_w, tid_g);
     HE_GLOBAL uint64_t *dst = as_global(jb.ct_out) + (size_t)plane * G::N;
     const uint64_t q = pk.q;
     constexpr int kMacOut = kF64 ? MacWsF64::kOutBoundX100 : MacAcc<A>::kOutBoundX100;
@@ -221,7 +225,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
           dst[(uint32_t)k] = s >= q ? s - q : s;
         }
       };
-      ntt_inverse_regs<A, G, kMacOut, false>(ar, twi, tid_g, lds_g, first, v, st);
+      ntt_inverse_regs<A, G, kMacOut, false, kWM>(ar, twi, tid_g, lds_g, first, v, st, twi_w);
     } else {
       // streaming stores: output planes are not read again by this launch
       // (addressed as the thread's part plus a compile-time part; the resource
@@ -229,7 +233,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       auto st = [&](int t, int c, uint64_t x) {
         if (valid) buf_store_u64_nt(buf_rsrc((const void *)dst, G::N * 8u), (uint32_t)t * 8u, (uint32_t)c * 8u, x);
       };
-      ntt_inverse_regs<A, G, kMacOut, false>(ar, twi, tid_g, lds_g, first, v, st);
+      ntt_inverse_regs<A, G, kMacOut, false, kWM>(ar, twi, tid_g, lds_g, first, v, st, twi_w);
     }
   }
 }

@@ -84,11 +84,13 @@ def test_twiddle_product_exact_and_bounded(q):
 @pytest.mark.parametrize("q", PRIMES)
 def test_product_with_formed_companion_exact_and_bounded(q):
     # mulv: the companion fl(b * fl(1/q)) formed in the kernel; b a residue of
-    # either sign (canonical, or a reduced double of the workspace)
+    # either sign (canonical, or a reduced double of the workspace), or a
+    # twiddle taken without its companion by a transform pass, whose inputs
+    # reach the 31 q limit
     rng = random.Random(q + 1)
     qf, qinv = float(q), 1.0 / float(q)
     bs = [q - 1, -(q - 1), int(REDUCED * q), -int(REDUCED * q), 1, -1] + [rng.randrange(-q + 1, q) for _ in range(20)]
-    for b_in in (0.51, 1.0, 4.0, 8.0):
+    for b_in in (0.51, 1.0, 4.0, 8.0, 16.0, 24.0, LIMIT):
         for y in operands(q, b_in, rng, 40):
             for b in bs:
                 r = mul(qf, y, float(b), float(b) * qinv)
