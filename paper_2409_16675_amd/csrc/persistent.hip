@@ -205,7 +205,8 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
     }
     hook();   // the operands are consumed: the next claim has long returned
     // (the first pass's twiddles are loaded here, not with the operands: held
-    // across the products they would push the kernel past its register budget)
+    // across the products they would push the kernel past its register budget;
+    // each later pass's twiddles are loaded during the pass before it)
     const auto twi = PTw<A>::inv(jb) + (size_t)i * G::N;
     // fp64: the passes whose lanes read different twiddles take them alone
     // (8 bytes, the quotient companion formed at the product)
@@ -225,7 +226,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
           dst[(uint32_t)k] = s >= q ? s - q : s;
         }
       };
-      ntt_inverse_regs<A, G, kMacOut, false, kWM>(ar, twi, tid_g, lds_g, first, v, st, twi_w);
+      ntt_inverse_regs<A, G, kMacOut, true, kWM>(ar, twi, tid_g, lds_g, first, v, st, twi_w);
     } else {
       // streaming stores: output planes are not read again by this launch
       // (addressed as the thread's part plus a compile-time part; the resource
@@ -233,7 +234,7 @@ __device__ __forceinline__ void run_task(const PTask &tk, const PJob &jb, int ti
       auto st = [&](int t, int c, uint64_t x) {
         if (valid) buf_store_u64_nt(buf_rsrc((const void *)dst, G::N * 8u), (uint32_t)t * 8u, (uint32_t)c * 8u, x);
       };
-      ntt_inverse_regs<A, G, kMacOut, false, kWM>(ar, twi, tid_g, lds_g, first, v, st, twi_w);
+      ntt_inverse_regs<A, G, kMacOut, true, kWM>(ar, twi, tid_g, lds_g, first, v, st, twi_w);
     }
   }
 }
