@@ -242,8 +242,8 @@ __device__ __forceinline__ int term_pt(const TermArgs &ta, int t) { return ta.ro
 template <class A, int LOGN, int LOGT, bool ACC, int NCOMP = 2>
 __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_mac_inv(
     uint64_t *__restrict__ out, const uint64_t *__restrict__ ct_hat, const uint64_t *__restrict__ pt_hat, TermArgs ta,
-    const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, int L, uint32_t xcd_chunk,
-    int n_planes) {
+    const PrimeK *__restrict__ primes, const typename A::Tw *__restrict__ tw, const double *__restrict__ tww, int L,
+    uint32_t xcd_chunk, int n_planes) {
   using G = Geo<LOGN, LOGT>;
   extern __shared__ __align__(16) unsigned char smem[];
   typename A::V *lds = reinterpret_cast<typename A::V *>(smem);
@@ -270,18 +270,22 @@ __global__ __launch_bounds__(1 << LOGT, (MinWaves<LOGN, LOGT>::value)) void k_ma
 #pragma unroll
   for (int e = 0; e < G::E; ++e) v[e] = acc[e].value();
   const typename A::Tw *twi = tw + (size_t)i * G::N;
-  PassTw<A, G, G::NPASS - 1, true> first;
-  first.load(twi, tid);
+  // fp64: the passes whose lanes read different twiddles take them alone
+  // (tww: the inverse twiddles without companions, formed at the product)
+  constexpr int kWM = std::is_same<A, ArF64>::value ? lane_passes<G>() : 0;
+  const double *twi_w = kWM ? tww + (size_t)i * G::N : nullptr;
+  PassTw<A, G, G::NPASS - 1, true, wbit<kWM, G::NPASS - 1>()> first;
+  first.load2(twi, twi_w, tid);
   uint64_t *dst = out + (size_t)plane * G::N;
   const uint64_t q = pk->q;
   if constexpr (ACC) {
     auto st = [&](int k, uint64_t x) { dst[(uint32_t)k] = canon_add(ar, dst[(uint32_t)k], x, q); };
-    ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100>(ar, twi, tid, lds, first, v, st);
+    ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100, true, kWM>(ar, twi, tid, lds, first, v, st, twi_w);
   } else {
     // output planes are not read again here: streaming stores keep them from
     // evicting the operands and twiddles that later planes reuse from L2
     auto st = [&](int k, uint64_t x) { __builtin_nontemporal_store(x, &dst[(uint32_t)k]); };
-    ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100>(ar, twi, tid, lds, first, v, st);
+    ntt_inverse_regs<A, G, MacAcc<A>::kOutBoundX100, true, kWM>(ar, twi, tid, lds, first, v, st, twi_w);
   }
 }
 
@@ -306,6 +310,12 @@ inline const TwF64 *tw_ptr<ArF64>(const Ctx &c, bool inverse) {
 template <>
 inline const TwU64 *tw_ptr<ArU64>(const Ctx &c, bool inverse) {
   return (const TwU64 *)(inverse ? c.d_tw_u64_inv : c.d_tw_u64_fwd);
+}
+
+// the inverse twiddles alone (fp64 only: the integer policy forms no companions)
+template <class A>
+static const double *tww_inv(const Ctx &c) {
+  return std::is_same<A, ArF64>::value ? c.d_tw_f64_inv_w : nullptr;
 }
 
 enum Op { OP_FWD, OP_FWD_LIFT, OP_INV, OP_MAC_INV, OP_FWD_SEEDED, OP_FWD_PACK, OP_FWD_CT_PACK, OP_FWD2 };
@@ -383,15 +393,15 @@ static hipError_t run_op(const Ctx &c, Op op, const LaunchArgs &la, hipStream_t 
         // single-component products (plaintext polynomials, tensor slots)
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, false, 1>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false, 1>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in,
-                           la.pt, la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
+                           la.pt, la.ta, c.d_primes, tw_ptr<A>(c, true), tww_inv<A>(c), (int)c.L, chunk, (int)la.grid);
       } else if (la.accumulate) {
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, true>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, true>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
-                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
+                           la.ta, c.d_primes, tw_ptr<A>(c, true), tww_inv<A>(c), (int)c.L, chunk, (int)la.grid);
       } else {
         if ((e = prep(k_mac_inv<A, LOGN, LOGT, false>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_mac_inv<A, LOGN, LOGT, false>), dim3(grid), dim3(G::NT), lds, st, la.out, la.in, la.pt,
-                           la.ta, c.d_primes, tw_ptr<A>(c, true), (int)c.L, chunk, (int)la.grid);
+                           la.ta, c.d_primes, tw_ptr<A>(c, true), tww_inv<A>(c), (int)c.L, chunk, (int)la.grid);
       }
       break;
     }
